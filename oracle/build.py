@@ -1,0 +1,112 @@
+"""FINGER construction (Algorithm 2) in float64.  Test infrastructure only.
+
+Follows Section 3.3 ("Low-rank Estimation", Eq. 3, Proposition 3.1,
+"Distribution Matching", "Overall Algorithm") and Algorithm 2, with these
+readings of the text:
+
+* Residuals.  Algorithm 2 writes cos(d, d') and cos(Pd, Pd') but the
+  quantities being modelled are angles between residuals w.r.t. the centre
+  node c (Section 3.2, Fig. 3/4 captions, Algorithm 3), so X and Y are taken
+  on d_res = d - (c.d / c.c) c and d'_res.
+* Sigma.  Algorithm 2 names the mean squared deviation sigma while
+  distribution matching scales by sigma / sigma_hat and speaks of matching
+  mean and variance; sigma is read as the population standard deviation
+  (the square root of Algorithm 2's quantity).  ``sigma_mode="variance"``
+  keeps the literal reading.
+* Basis.  P = U_{1:r}^T from the SVD of D_res (m x N), uncentred
+  (Proposition 3.1).  Only the row space of P matters downstream: every
+  estimate uses cosines of P-projections, unchanged by signs or rotations
+  of P's rows.
+* Degenerate vectors.  c.c = 0 gives no projection (alpha = 0); a cosine
+  with a zero vector is 0; sigma_hat = 0 makes the scale factor 1.
+* Samples.  One pair per sampled node; N_s = min(n, n_samples) nodes drawn
+  by ``oracle.rng.sample_pairs``; only d_res enters D_res.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .rng import sample_pairs
+
+
+def split(x: np.ndarray, c: np.ndarray):
+    """Eq. 1: x = x_proj + x_res with x_proj = (c.x / c.c) c.  Rows of x
+    (.., m) share one centre c (m,).  Returns (alpha, x_proj, x_res)."""
+    x = np.asarray(x, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    cc = float(c @ c)
+    alpha = (x @ c) / cc if cc > 0 else np.zeros(x.shape[:-1])
+    proj = np.multiply.outer(alpha, c)
+    return alpha, proj, x - proj
+
+
+def cosine_rows(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Row-wise cosine; 0 where either row is the zero vector."""
+    num = (A * B).sum(-1)
+    den = np.sqrt((A * A).sum(-1) * (B * B).sum(-1))
+    return np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+
+
+def residual_pairs(data: np.ndarray, c: np.ndarray, d: np.ndarray,
+                   dp: np.ndarray):
+    """d_res and d'_res of each sample w.r.t. its own centre (Eq. 1)."""
+    C = np.asarray(data[c], dtype=np.float64)
+    D = np.asarray(data[d], dtype=np.float64)
+    Dp = np.asarray(data[dp], dtype=np.float64)
+    cc = (C * C).sum(1)
+    safe = np.where(cc > 0, cc, 1.0)
+    a = np.where(cc > 0, (D * C).sum(1) / safe, 0.0)
+    ap = np.where(cc > 0, (Dp * C).sum(1) / safe, 0.0)
+    return D - a[:, None] * C, Dp - ap[:, None] * C
+
+
+def basis_from_residuals(Dres_rows: np.ndarray, rank: int) -> tuple[np.ndarray, np.ndarray]:
+    """Proposition 3.1: the first r left singular vectors of D_res (m x N)
+    as the rows of P.  Returns (P [r, m], singular values)."""
+    U, S, _ = np.linalg.svd(Dres_rows.T, full_matrices=False)
+    return U[:, :rank].T.copy(), S
+
+
+def dm_stats(X: np.ndarray, Y: np.ndarray, sigma_mode: str = "std"):
+    """Distribution matching statistics of Algorithm 2: means, spreads and
+    the mean absolute error after matching (the correction term epsilon)."""
+    N = X.shape[0]
+    mu = X.sum() / N
+    mu_hat = Y.sum() / N
+    var = ((X - mu) ** 2).sum() / N
+    var_hat = ((Y - mu_hat) ** 2).sum() / N
+    if sigma_mode == "std":
+        sigma, sigma_hat = np.sqrt(var), np.sqrt(var_hat)
+    elif sigma_mode == "variance":
+        sigma, sigma_hat = var, var_hat
+    else:
+        raise ValueError(sigma_mode)
+    scale = sigma / sigma_hat if sigma_hat > 0 else 1.0
+    eps = np.abs((Y - mu_hat) * scale + mu - X).sum() / N
+    return dict(mu=float(mu), sigma=float(sigma), mu_hat=float(mu_hat),
+                sigma_hat=float(sigma_hat), eps=float(eps))
+
+
+def build(data: np.ndarray, graph: np.ndarray, rank: int,
+          n_samples: int = 100_000, seed: int = 0,
+          sigma_mode: str = "std") -> dict:
+    """Algorithm 2.  Returns P (r x m, float64), the five distribution
+    parameters and the intermediate samples for inspection."""
+    c, d, dp, idx = sample_pairs(graph, n_samples, seed)
+    Dres, Dres2 = residual_pairs(data, c, d, dp)
+    P, S = basis_from_residuals(Dres, rank)
+    X = cosine_rows(Dres, Dres2)
+    Y = cosine_rows(Dres @ P.T, Dres2 @ P.T)
+    out = dm_stats(X, Y, sigma_mode)
+    out.update(P=P, singular_values=S, X=X, Y=Y,
+               samples=(c, d, dp, idx), rank=rank)
+    return out
+
+
+def identity_dm(tables: dict) -> dict:
+    """Copy of ``tables`` with distribution matching switched off
+    (mu = mu_hat = 0, sigma = sigma_hat = 1, eps = 0): the low-rank-only
+    estimate of the ablation study (Section 4.3)."""
+    t = dict(tables)
+    t.update(mu=0.0, sigma=1.0, mu_hat=0.0, sigma_hat=1.0, eps=0.0)
+    return t

@@ -1,0 +1,98 @@
+"""Seeded point-set generators.
+
+Every generator draws from ``numpy.random.default_rng(seed)`` in a fixed order
+(centres, data labels, data noise, query labels, query noise) so a workload is
+fully determined by its spec.  The mixtures stand in for the shapes and value
+distributions of the paper's benchmark sets (Section 4.1: SIFT-1M-128,
+GIST-1M-960, GloVe-1.2M-100, DEEP-10M-96); none of those sets' items are used.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class WorkloadSpec:
+    """A point-set recipe.
+
+    kind:
+      "gauss"   centres ~ N(0, I), x = centre + sigma * N(0, I)            (float)
+      "int"     centres ~ U[0, 128)^m, x = clip(rint(centre + sigma*N), 0, 255)
+      "uniform" centres ~ U[0, 1)^m,   x = centre + sigma * N(0, I)
+      "heavy"   centres ~ N(0, I), x = centre + sigma * Student-t(3), unit-normalised
+    """
+
+    name: str
+    kind: str
+    n: int
+    m: int
+    n_centers: int
+    sigma: float
+    nq: int
+    seed: int = 0
+    knn_k: int = 16          # exact kNN size before symmetrization
+    max_degree: int = 32     # graph row width after pruning
+    extra: dict = field(default_factory=dict)
+
+    def scaled(self, n: int | None = None, nq: int | None = None,
+               n_centers: int | None = None, **kw) -> "WorkloadSpec":
+        return replace(self,
+                       n=self.n if n is None else n,
+                       nq=self.nq if nq is None else nq,
+                       n_centers=self.n_centers if n_centers is None else n_centers,
+                       **kw)
+
+
+SPECS = {
+    # parity workload: 100 isotropic Gaussians in 32-d
+    "c1": WorkloadSpec("c1", "gauss", 10_000, 32, 100, 0.3, 1_000, seed=0),
+    # bandwidth workload: integer-valued 128-d, 1000 clusters
+    "c2": WorkloadSpec("c2", "int", 1_000_000, 128, 1_000, 24.0, 10_000, seed=0),
+    # precision workloads
+    "c3a": WorkloadSpec("c3a", "uniform", 1_000_000, 960, 1_000, 0.1, 10_000, seed=0),
+    "c3b": WorkloadSpec("c3b", "heavy", 1_200_000, 100, 1_000, 1.0, 10_000, seed=0),
+    # batching workload
+    "c4": WorkloadSpec("c4", "gauss", 10_000_000, 96, 10_000, 0.5, 100_000, seed=0),
+}
+
+
+def _draw(rng: np.random.Generator, spec: WorkloadSpec, centers: np.ndarray,
+          count: int) -> np.ndarray:
+    labels = rng.integers(0, spec.n_centers, size=count)
+    m = spec.m
+    out = np.empty((count, m), dtype=np.float32)
+    step = 1 << 16
+    for s in range(0, count, step):
+        e = min(count, s + step)
+        c = centers[labels[s:e]]
+        if spec.kind == "heavy":
+            noise = rng.standard_t(3.0, size=(e - s, m))
+        else:
+            noise = rng.standard_normal(size=(e - s, m))
+        x = c + spec.sigma * noise
+        if spec.kind == "int":
+            x = np.clip(np.rint(x), 0, 255)
+        elif spec.kind == "heavy":
+            nrm = np.sqrt((x * x).sum(axis=1, keepdims=True))
+            nrm[nrm == 0] = 1.0
+            x = x / nrm
+        out[s:e] = x.astype(np.float32)
+    return out
+
+
+def make_points(spec: WorkloadSpec) -> tuple[np.ndarray, np.ndarray]:
+    """Return (data [n, m], queries [nq, m]) as C-contiguous float32."""
+    rng = np.random.default_rng(spec.seed)
+    if spec.kind == "gauss" or spec.kind == "heavy":
+        centers = rng.standard_normal(size=(spec.n_centers, spec.m))
+    elif spec.kind == "int":
+        centers = rng.uniform(0.0, 128.0, size=(spec.n_centers, spec.m))
+    elif spec.kind == "uniform":
+        centers = rng.uniform(0.0, 1.0, size=(spec.n_centers, spec.m))
+    else:
+        raise ValueError(f"unknown kind {spec.kind}")
+    data = _draw(rng, spec, centers, spec.n)
+    queries = _draw(rng, spec, centers, spec.nq)
+    return np.ascontiguousarray(data), np.ascontiguousarray(queries)
