@@ -1,0 +1,345 @@
+/*
+ * finger.h - C ABI of libfinger, an MI355X (gfx950) implementation of FINGER
+ * search: greedy beam search over a proximity graph in which the exact L2
+ * distance to each neighbour is first screened by FINGER's low-rank +
+ * distribution-matching estimate (Chen et al., "FINGER: Fast Inference for
+ * Graph-based Approximate Nearest Neighbor Search").
+ *
+ * Conventions for every entry point below:
+ *   - Pointers are DEVICE pointers unless marked (host).  Arrays are dense,
+ *     row-major, with the stated element type.
+ *   - Every call returns an int status: FINGER_OK (0) or a negative
+ *     finger_status.  Nothing aborts or throws across the ABI.  On error the
+ *     outputs are undefined, any handle stays valid, and finger_last_error()
+ *     returns a message for the calling thread.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls marked "async" only enqueue work on it; the caller synchronizes.
+ *   - The library never allocates device memory inside finger_search or
+ *     finger_exact_knn: scratch space comes from the caller's workspace.
+ *
+ * Problem statement (Section 1): a dataset D of n points with m features, a
+ * query q, the K closest points of D under squared L2 distance; recall@K =
+ * |T intersect A| / K.
+ */
+#ifndef FINGER_H
+#define FINGER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define FINGER_API __attribute__((visibility("default")))
+#else
+#define FINGER_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FINGER_OK = 0,
+  FINGER_EINVAL = -1,     /* invalid argument; message names it */
+  FINGER_ENOMEM = -2,     /* device or host allocation failed */
+  FINGER_EDEVICE = -3,    /* a HIP call failed; message has the HIP error */
+  FINGER_ENODEV = -4,     /* no usable gfx950 device */
+  FINGER_EOVERFLOW = -5,  /* a fixed capacity (LDS, table) cannot hold the request */
+  FINGER_EINTERNAL = -6
+} finger_status;
+
+typedef enum {
+  FINGER_L2 = 0,          /* squared Euclidean distance */
+  FINGER_ANGULAR = 1      /* squared L2 between unit-normalized vectors
+                             (Supplementary A: normalize, then the same
+                             decomposition); 1 - cos = d2 / 2 */
+} finger_metric;
+
+typedef enum {
+  FINGER_CODE_F32 = 0,    /* u_d stored as float: (r+2)*|E|*4 bytes (Suppl. F) */
+  FINGER_CODE_BF16 = 1,   /* u_d rounded to bfloat16 (nearest-even) */
+  FINGER_CODE_FP8E4M3 = 2 /* u_d / s_c rounded to OCP FP8 E4M3, s_c = per-node scale */
+} finger_code_t;
+
+typedef enum {
+  FINGER_MODE_PLAIN = 0,  /* greedy graph search, Algorithm 1 */
+  FINGER_MODE_FINGER = 1, /* approximate greedy search, Algorithm 4 */
+  FINGER_MODE_GATED = 2   /* Algorithm 4 with the learned gate replacing the
+                             distribution-matching map (needs finger_gate_attach) */
+} finger_mode;
+
+typedef enum {
+  FINGER_SIGMA_STD = 0,      /* sigma = population standard deviation */
+  FINGER_SIGMA_VARIANCE = 1  /* sigma = the mean squared deviation, as Algorithm 2 prints it */
+} finger_sigma_mode;
+
+/* Counters written per query by finger_search (int32 [nq][FINGER_NCOUNTERS]). */
+enum {
+  FINGER_CTR_EXPANSIONS = 0, /* nodes expanded (Algorithm 1's outer loop) */
+  FINGER_CTR_EXACT = 1,      /* exact distances computed, the entry included */
+  FINGER_CTR_SCREENED = 2,   /* neighbours screened by the estimate */
+  FINGER_CTR_SKIPPED = 3,    /* screened neighbours whose estimate exceeded ub */
+  FINGER_CTR_VISITED = 4,    /* |V| at the end */
+  FINGER_CTR_STATUS = 5,     /* 0 = ok; 1 = visited-set capacity reached (search
+                                stopped early; raise visited_capacity) */
+  FINGER_NCOUNTERS = 6
+};
+
+/* ---------------------------------------------------------------- build */
+
+typedef struct finger_build_params {
+  int32_t rank;          /* r (Section 3.3), 0 <= r <= m and r <= 256;
+                            0 builds a plain-search-only handle */
+  int32_t code_type;     /* finger_code_t */
+  int32_t metric;        /* finger_metric */
+  int32_t sigma_mode;    /* finger_sigma_mode */
+  int64_t n_samples;     /* sampled nodes N_s; <= 0 means min(n, 100000) */
+  uint64_t seed;         /* SplitMix64 seed for the samples (see below) */
+  const int32_t* pivots; /* device int32 [n_pivots] node ids, or NULL.  With
+                            pivots a search may start each query at its
+                            nearest pivot (entry = -1). */
+  int32_t n_pivots;      /* 0..65536 */
+  int32_t dm_override;   /* 1: use dm[] instead of the measured statistics */
+  double dm[5];          /* mu, sigma, mu_hat, sigma_hat, eps (override) */
+} finger_build_params;
+
+/* Fill *p with the defaults (rank 0, F32 codes, L2, sigma = std, N_s = min(n,
+ * 100000), seed 0, no pivots, no override). */
+FINGER_API void finger_build_params_init(finger_build_params* p /* host */);
+
+typedef struct finger_tables finger_tables; /* opaque handle */
+
+/*
+ * finger_build_tables - FINGER construction, Algorithm 2 with the
+ * precomputation of Supplementary G.  Synchronous on return.
+ *
+ *   data  [n][m] float: the dataset D.  Borrowed: must stay valid and
+ *         unchanged until finger_free_tables (for FINGER_ANGULAR the handle
+ *         keeps its own normalized copy instead).
+ *   graph [n][max_degree] int32: out-neighbours of each node, valid ids
+ *         first, then -1 padding; no self loops, no repeated ids in a row.
+ *         Borrowed like data.  1 <= max_degree <= 64.
+ *   m     1..2048, a multiple of 4, data 16-byte aligned.
+ *
+ * Sampling: N_s samples; sample i uses node c = i when N_s == n, else
+ * c = h(3i) mod n, where h(j) is the j-th output of SplitMix64 seeded with
+ * `seed`; nodes with fewer than 2 neighbours are dropped; the neighbour pair
+ * is slots a = h(3i+1) mod deg and (a + 1 + h(3i+2) mod (deg-1)) mod deg.
+ * Residuals d_res = d - (c.d / c.c) c (Eq. 1) of the first neighbour form
+ * D_res; P holds the top-r eigenvectors of D_res D_res^T (the left singular
+ * vectors of Proposition 3.1, computed in float64).  X and Y are the cosines
+ * of (d_res, d'_res) and of their projections; mu, sigma, mu_hat, sigma_hat
+ * and eps follow Algorithm 2, accumulated in float64.
+ * Per node: c.c and P c.  Per edge slot (c -> d): alpha_d = c.d / c.c,
+ * rho_d = ||d_res||, u_d = P d_res / ||P d_res|| (0 if that norm is 0), i.e.
+ * (r+2) values per edge (Supplementary F); -1 slots hold zeros.
+ *
+ * Errors: EINVAL (n <= 0, m out of range, max_degree out of range, rank out
+ * of range, bad code_type/metric/sigma_mode, a graph id out of range, a self
+ * loop or repeated id, a pivot out of range, NULL pointers), ENOMEM,
+ * EDEVICE, ENODEV.
+ */
+FINGER_API int finger_build_tables(const float* data, int64_t n, int32_t m,
+                        const int32_t* graph, int32_t max_degree,
+                        const finger_build_params* p /* host */,
+                        finger_tables** out /* host */, void* stream);
+
+/* Release a handle and everything it owns (NULL is a no-op). */
+FINGER_API void finger_free_tables(finger_tables* t);
+
+typedef struct finger_tables_info {
+  int64_t n;
+  int32_t m, rank, max_degree, code_type, metric, n_pivots;
+  int64_t n_samples_used;   /* samples kept after dropping degree < 2 nodes */
+  double mu, sigma, mu_hat, sigma_hat, eps; /* the constants the search uses */
+  double eps_gate;          /* learned-gate correction (0 if no gate) */
+  int32_t gate_attached;
+  int64_t edge_table_bytes; /* bytes of alpha, rho and u over all slots */
+} finger_tables_info;
+
+FINGER_API int finger_tables_info_get(const finger_tables* t, finger_tables_info* info /* host */);
+
+/* Selectors for finger_tables_read (sizes in elements):
+ *   P_F64      double [r][m]     basis (rows = eigenvectors, descending eigenvalue)
+ *   EIGVALS    double [m]        eigenvalues of D_res D_res^T, descending
+ *   P_F32      float  [r][m]     basis used by the kernels
+ *   NODE_CC    float  [n]        c.c
+ *   NODE_PC    float  [n][r]     P c
+ *   EDGE_ALPHA float  [n][deg]   alpha_d
+ *   EDGE_RHO   float  [n][deg]   rho_d
+ *   EDGE_CODES raw    [n][deg][r] u_d as stored (float, bf16 bits or fp8 bytes)
+ *   EDGE_SCALE float  [n]        FP8 per-node scale (1 for other code types)
+ *   SAMPLES    int32  [N][3]     kept samples (c, d, d')
+ *   XY         double [N][2]     (X_i, Y_i) per kept sample
+ */
+enum {
+  FINGER_T_P_F64 = 0, FINGER_T_EIGVALS = 1, FINGER_T_P_F32 = 2, FINGER_T_NODE_CC = 3,
+  FINGER_T_NODE_PC = 4, FINGER_T_EDGE_ALPHA = 5, FINGER_T_EDGE_RHO = 6,
+  FINGER_T_EDGE_CODES = 7, FINGER_T_EDGE_SCALE = 8, FINGER_T_SAMPLES = 9, FINGER_T_XY = 10
+};
+
+/* Copy one table to host memory.  *bytes (host) in: capacity of dst; out:
+ * the table's size.  dst == NULL only queries the size.  EINVAL for an
+ * unknown selector, EOVERFLOW if the capacity is too small.  Synchronous. */
+FINGER_API int finger_tables_read(const finger_tables* t, int32_t which, void* dst /* host */,
+                       size_t* bytes /* host */);
+
+/* --------------------------------------------------------------- search */
+
+typedef struct finger_search_params {
+  int32_t mode;          /* finger_mode */
+  int32_t k;             /* K for every query (ignored with k_per_query) */
+  int32_t ef;            /* efs for every query (ignored with ef_per_query);
+                            the search keeps ef_eff = max(ef, K) entries */
+  int32_t entry;         /* >= 0: start point p of every query (Algorithm 1);
+                            -1: each query starts at its nearest pivot */
+  int32_t warmup;        /* W: screening starts once more than W nodes have
+                            been expanded (Algorithm 4's "> 5 updates"); < 0 = 5 */
+  int32_t k_max;         /* row stride of out_ids/out_dist; >= every K */
+  const int32_t* k_per_query;  /* device int32 [nq] or NULL */
+  const int32_t* ef_per_query; /* device int32 [nq] or NULL */
+  int32_t ef_max;        /* >= ef_eff of every query; 0 = derive from k/ef
+                            (required when ef_per_query or k_per_query is set) */
+  int32_t persistent;    /* 1: one launch drains an atomic queue of queries
+                            (uneven K/ef); 0: static assignment */
+  int32_t waves_per_cu;  /* resident query waves per CU; 0 = library default */
+  int32_t visited_capacity; /* visited-set slots per query (power of two,
+                               >= 256); 0 = default from ef_max */
+  /* Gate-training log (mode FINGER only; NULL = off).  For every screened
+   * neighbour the kernel appends one row of FINGER_GATE_FEATURES(r) floats
+   * (see finger_gate_attach) to log_features, its exact squared distance
+   * and the screening bound to log_targets ([row][2]: d2, ub2) and counts rows in
+   * *log_count (int64); rows past log_capacity are counted, not written. */
+  float* log_features;
+  float* log_targets;
+  int64_t log_capacity;
+  int64_t* log_count;
+} finger_search_params;
+
+FINGER_API void finger_search_params_init(finger_search_params* p /* host */);
+
+/* Bytes of device workspace finger_search needs for nq queries.  EINVAL as
+ * for finger_search. */
+FINGER_API int finger_search_workspace_size(const finger_tables* t, int64_t nq,
+                                 const finger_search_params* p /* host */,
+                                 size_t* bytes /* host */);
+
+/*
+ * finger_search - batched greedy search (Algorithm 1) or FINGER search
+ * (Algorithm 4 with Algorithm 3's estimate), one wavefront per query.  Async.
+ *
+ *   queries      [nq][m] float.
+ *   out_ids      [nq][k_max] int32: the K best (d2, id) of T in ascending
+ *                order; slots past K or past |T| hold -1.
+ *   out_dist     [nq][k_max] float: their squared distances (+inf padding).
+ *   out_counters [nq][FINGER_NCOUNTERS] int32, or NULL.
+ *   workspace    >= finger_search_workspace_size bytes, 256-byte aligned.
+ *
+ * Semantics (each a reading of the pseudo-code): keys are (d2, id); a
+ * neighbour is admitted iff |T| < ef_eff or its key is below the worst key
+ * of T; the search ends when T has no unexpanded entry.  FINGER screens the
+ * unvisited neighbours of an expansion only when T is full and more than W
+ * nodes have been expanded, against ub = worst d2 of T at the start of that
+ * expansion; a neighbour is skipped iff its estimate exceeds ub (it stays
+ * visited); survivors get exact distances and the admission rule above.
+ * Returned distances are always exact (Supplementary G).
+ *
+ * Errors: EINVAL (nq < 0, k < 1 or k > n, ef < 1, entry out of range,
+ * entry = -1 without pivots, FINGER/GATED mode on a rank-0 handle, GATED
+ * without a gate, workspace too small or misaligned, ef_max > 1024, NULL
+ * pointers), EOVERFLOW (ef_max or visited_capacity beyond the LDS budget),
+ * EDEVICE.
+ */
+FINGER_API int finger_search(const finger_tables* t, const float* queries, int64_t nq,
+                  const finger_search_params* p /* host */,
+                  int32_t* out_ids, float* out_dist, int32_t* out_counters,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * finger_estimate_edges - evaluate the search kernel's estimate for given
+ * (query, centre, edge slot) triples, for testing the factorized arithmetic
+ * against a direct evaluation.  Async.
+ *   q_index, centers, slots [n_items] int32 (device); slot indexes the centre's
+ *   graph row and must hold a valid neighbour.
+ *   out_est   [n_items] float: the estimated squared distance (Algorithm 3
+ *             plugged into Eq. 2), computed exactly as finger_search does.
+ *   out_t_hat [n_items] float: the low-rank cosine cos(P q_res, P d_res).
+ * Errors: EINVAL (rank-0 handle, NULL pointers, n_items < 0), EDEVICE.
+ * Indices are not range-checked on the device: the caller guarantees them.
+ */
+FINGER_API int finger_estimate_edges(const finger_tables* t, const float* queries, int64_t nq,
+                          const int32_t* q_index, const int32_t* centers,
+                          const int32_t* slots, int64_t n_items,
+                          float* out_est, float* out_t_hat, void* stream);
+
+/* ----------------------------------------------------------- exact kNN */
+
+/* Workspace for finger_exact_knn. */
+FINGER_API int finger_exact_knn_workspace_size(int64_t n, int32_t m, int64_t nq, int32_t k,
+                                    size_t* bytes /* host */);
+
+/*
+ * finger_exact_knn - brute-force K nearest neighbours (the ground truth A of
+ * recall@K, Section 1).  Candidates are selected with an MFMA GEMM
+ * (|q|^2 + |x|^2 - 2 q.x), the best K+32 per query are re-ranked by direct
+ * differences in float32 and returned sorted by (d2, id).  Async.
+ *   data [n][m], queries [nq][m] float; out_ids int32 / out_dist float
+ *   [nq][k].  k <= n, k <= 256.  FINGER_ANGULAR normalizes both sides.
+ * Errors: EINVAL, EDEVICE.
+ */
+FINGER_API int finger_exact_knn(const float* data, int64_t n, int32_t m,
+                     const float* queries, int64_t nq, int32_t k, int32_t metric,
+                     int32_t* out_ids, float* out_dist,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------ learned skip gate */
+
+/*
+ * The gate is an extension beyond the paper: a 3-layer perceptron
+ * (in -> H -> H -> 1, ReLU) that maps screening features to an estimate of
+ * cos(q_res, d_res), used in place of Algorithm 3's distribution-matching map.
+ * Features of one screened edge (in = 2r + 4, all float):
+ *   [0, r)      w / |w|, w = P q_res = Pq - alpha_q P c   (0 if |w| = 0)
+ *   [r, 2r)     u_d
+ *   2r          t_hat = w.u_d / |w|
+ *   2r + 1      rho_q / ub        (ub = sqrt of the screening bound)
+ *   2r + 2      rho_d / ub
+ *   2r + 3      (alpha_q - alpha_d)^2 c.c / ub^2
+ * The gated estimate is Eq. 2 with t = f(x) + eps_gate.
+ */
+#define FINGER_GATE_FEATURES(r) (2 * (r) + 4)
+
+/* Weight layout (float, host): W1 [H][in], b1 [H], W2 [H][H], b2 [H],
+ * W3 [H], b3 [1]; 1 <= H <= 64 and in == FINGER_GATE_FEATURES(rank).  The
+ * handle keeps a bf16 copy used by the search kernel.  Synchronous. */
+FINGER_API int finger_gate_attach(finger_tables* t, const float* weights /* host */,
+                       int32_t in_dim, int32_t hidden, double eps_gate);
+
+/* Number of floats in the weight layout above. */
+FINGER_API int64_t finger_gate_param_count(int32_t in_dim, int32_t hidden);
+
+/*
+ * Training kernels (bf16 operands, float32 accumulation).  Weights, grads and
+ * Adam moments are float [P] in the layout above (device).
+ *   finger_mlp_forward:  x [B][in] float -> y [B] float.
+ *   finger_mlp_backward: loss = mean over the batch of (y - target)^2;
+ *                        writes grad [P] (overwritten) and *loss (device float).
+ *   finger_adam_step:    Adam (Kingma & Ba) with bias correction at step t >= 1.
+ * Async.  Errors: EINVAL (sizes, NULL pointers), EDEVICE.
+ */
+FINGER_API int finger_mlp_forward(const float* weights, int32_t in_dim, int32_t hidden,
+                       const float* x, int64_t batch, float* y, void* stream);
+FINGER_API int finger_mlp_backward(const float* weights, int32_t in_dim, int32_t hidden,
+                        const float* x, const float* target, int64_t batch,
+                        float* grad, float* loss, void* stream);
+FINGER_API int finger_adam_step(float* weights, const float* grad, float* m1, float* m2,
+                     int64_t count, float lr, float beta1, float beta2, float eps,
+                     int32_t step, void* stream);
+
+/* Message for the last failed call on this thread ("" if none). */
+FINGER_API const char* finger_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FINGER_H */

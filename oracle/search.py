@@ -161,6 +161,18 @@ def search(data: np.ndarray, graph: np.ndarray, q: np.ndarray, entry: int,
     return ids, d2, cnt, margin
 
 
+def pivot_entries(queries: np.ndarray, data: np.ndarray, pivots: np.ndarray) -> np.ndarray:
+    """Start point p of each query (Algorithm 1's input) when it is chosen
+    among pivot nodes: the pivot at the smallest exact squared distance,
+    ties to the earlier pivot in the list.  (A flat stand-in for the upper
+    layers of the HNSW graph the paper searches.)"""
+    P = np.asarray(data[pivots], dtype=np.float64)
+    out = np.empty(np.atleast_2d(queries).shape[0], dtype=np.int64)
+    for i, q in enumerate(np.atleast_2d(queries)):
+        out[i] = pivots[int(np.argmin(sqdist(q, P)))]
+    return out
+
+
 def search_batch(data, graph, queries, entries, ef, k, **kw):
     """``search`` over many queries.  ``entries`` is one id or one per query;
     ``ef``/``k`` are scalars or per-query sequences.  Returns (ids [nq, kmax],

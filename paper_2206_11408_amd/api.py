@@ -1,0 +1,250 @@
+"""Python binding of libfinger with the C entry points' names.
+
+Only argument marshalling happens here: torch supplies device memory and
+the current HIP stream; every step of build and search runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _dev_i32(x, device="cuda") -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.int32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.int32, device=device)
+
+
+def _dev_f32(x, device="cuda") -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device=device)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator hands out 512-byte aligned blocks
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+class Tables:
+    """Owns a finger_tables handle and keeps the borrowed data/graph alive."""
+
+    def __init__(self, handle: int, data: torch.Tensor, graph: torch.Tensor, extra=()):
+        self.handle = handle
+        self._keep = (data, graph, *extra)
+        self.data = data
+        self.graph = graph
+        self._ws = None
+
+    def info(self) -> dict:
+        inf = L.TablesInfo()
+        L.check(L.load().finger_tables_info_get(self.handle, C.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in L.TablesInfo._fields_}
+
+    def read(self, which: int) -> np.ndarray:
+        """finger_tables_read into a numpy array of the table's element type."""
+        lib = L.load()
+        nbytes = C.c_size_t(0)
+        L.check(lib.finger_tables_read(self.handle, which, None, C.byref(nbytes)))
+        buf = np.empty(nbytes.value, dtype=np.uint8)
+        L.check(lib.finger_tables_read(self.handle, which, buf.ctypes.data, C.byref(nbytes)))
+        inf = self.info()
+        n, m, r, deg = inf["n"], inf["m"], inf["rank"], inf["max_degree"]
+        rpad = (r + 15) // 16 * 16
+        if which in (L.T_P_F64,):
+            return buf.view(np.float64).reshape(r, m)
+        if which == L.T_EIGVALS:
+            return buf.view(np.float64)
+        if which == L.T_P_F32:
+            return buf.view(np.float32).reshape(r, m)
+        if which == L.T_NODE_CC:
+            return buf.view(np.float32)
+        if which == L.T_NODE_PC:
+            return buf.view(np.float32).reshape(n, r)
+        if which in (L.T_EDGE_ALPHA, L.T_EDGE_RHO):
+            return buf.view(np.float32).reshape(n, deg)
+        if which == L.T_EDGE_CODES:
+            dt = {L.CODE_F32: np.float32, L.CODE_BF16: np.uint16, L.CODE_FP8E4M3: np.uint8}[inf["code_type"]]
+            return buf.view(dt).reshape(n, deg, rpad)
+        if which == L.T_EDGE_SCALE:
+            return buf.view(np.float32)
+        if which == L.T_SAMPLES:
+            return buf.view(np.int32).reshape(-1, 3)
+        if which == L.T_XY:
+            return buf.view(np.float64).reshape(-1, 2)
+        return buf
+
+    def close(self) -> None:
+        if self.handle:
+            L.load().finger_free_tables(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def finger_build_tables(data: torch.Tensor, graph: torch.Tensor, rank: int = 0,
+                        code_type: int = L.CODE_F32, metric: int = L.L2,
+                        sigma_mode: int = L.SIGMA_STD, n_samples: int = 0, seed: int = 0,
+                        pivots=None, dm_override=None) -> Tables:
+    lib = L.load()
+    data = _dev_f32(data)
+    graph = _dev_i32(graph)
+    n, m = data.shape
+    deg = graph.shape[1]
+    p = L.BuildParams()
+    lib.finger_build_params_init(C.byref(p))
+    p.rank = rank
+    p.code_type = code_type
+    p.metric = metric
+    p.sigma_mode = sigma_mode
+    p.n_samples = n_samples
+    p.seed = seed
+    piv = None
+    if pivots is not None:
+        piv = _dev_i32(pivots)
+        p.pivots = piv.data_ptr()
+        p.n_pivots = piv.numel()
+    if dm_override is not None:
+        p.dm_override = 1
+        for i, v in enumerate(dm_override):
+            p.dm[i] = float(v)
+    h = C.c_void_p()
+    L.check(lib.finger_build_tables(data.data_ptr(), n, m, graph.data_ptr(), deg, C.byref(p),
+                                    C.byref(h), _stream()))
+    return Tables(h.value, data, graph, (piv,) if piv is not None else ())
+
+
+def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
+                  k_per_query=None, ef_per_query=None, ef_max=0, persistent=0,
+                  waves_per_cu=0, visited_capacity=0, log=None) -> L.SearchParams:
+    p = L.SearchParams()
+    L.load().finger_search_params_init(C.byref(p))
+    p.mode, p.k, p.ef, p.entry, p.warmup = mode, k, ef, entry, warmup
+    p.k_max = k if k_max is None else k_max
+    p.k_per_query = _ptr(k_per_query)
+    p.ef_per_query = _ptr(ef_per_query)
+    p.ef_max, p.persistent = ef_max, persistent
+    p.waves_per_cu, p.visited_capacity = waves_per_cu, visited_capacity
+    if log is not None:
+        feats, targs, count = log
+        p.log_features, p.log_targets = feats.data_ptr(), targs.data_ptr()
+        p.log_capacity = feats.shape[0]
+        p.log_count = count.data_ptr()
+    return p
+
+
+def finger_search_workspace_size(tables: Tables, nq: int, p: L.SearchParams) -> int:
+    nbytes = C.c_size_t(0)
+    L.check(L.load().finger_search_workspace_size(tables.handle, nq, C.byref(p), C.byref(nbytes)))
+    return nbytes.value
+
+
+def finger_search(tables: Tables, queries: torch.Tensor, p: L.SearchParams | None = None,
+                  out=None, counters: bool = True, **kw):
+    """Run finger_search; returns (ids int32 [nq, k_max], dist f32 [nq, k_max],
+    counters int32 [nq, 6] or None).  Pass ``out=(ids, dist, ctr)`` to reuse
+    buffers (timing loops)."""
+    lib = L.load()
+    if p is None:
+        p = search_params(**kw)
+    queries = _dev_f32(queries)
+    nq = queries.shape[0]
+    need = finger_search_workspace_size(tables, nq, p)
+    if tables._ws is None or tables._ws.numel() < need:
+        tables._ws = _workspace(need, queries.device)
+    if out is None:
+        ids = torch.empty((nq, p.k_max), dtype=torch.int32, device=queries.device)
+        dist = torch.empty((nq, p.k_max), dtype=torch.float32, device=queries.device)
+        ctr = torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=queries.device) if counters else None
+    else:
+        ids, dist, ctr = out
+    L.check(lib.finger_search(tables.handle, queries.data_ptr(), nq, C.byref(p), ids.data_ptr(),
+                              dist.data_ptr(), _ptr(ctr), tables._ws.data_ptr(),
+                              tables._ws.numel(), _stream()))
+    return ids, dist, ctr
+
+
+def finger_estimate_edges(tables: Tables, queries: torch.Tensor, q_index, centers, slots):
+    lib = L.load()
+    queries = _dev_f32(queries)
+    qi, ci, si = _dev_i32(q_index), _dev_i32(centers), _dev_i32(slots)
+    n_items = qi.numel()
+    est = torch.empty(n_items, dtype=torch.float32, device=queries.device)
+    that = torch.empty(n_items, dtype=torch.float32, device=queries.device)
+    L.check(lib.finger_estimate_edges(tables.handle, queries.data_ptr(), queries.shape[0],
+                                      qi.data_ptr(), ci.data_ptr(), si.data_ptr(), n_items,
+                                      est.data_ptr(), that.data_ptr(), _stream()))
+    return est, that
+
+
+def finger_exact_knn(data: torch.Tensor, queries: torch.Tensor, k: int, metric: int = L.L2):
+    lib = L.load()
+    data = _dev_f32(data)
+    queries = _dev_f32(queries)
+    n, m = data.shape
+    nq = queries.shape[0]
+    nbytes = C.c_size_t(0)
+    L.check(lib.finger_exact_knn_workspace_size(n, m, nq, k, C.byref(nbytes)))
+    ws = _workspace(nbytes.value, data.device)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=data.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=data.device)
+    L.check(lib.finger_exact_knn(data.data_ptr(), n, m, queries.data_ptr(), nq, k, metric,
+                                 ids.data_ptr(), dist.data_ptr(), ws.data_ptr(), ws.numel(),
+                                 _stream()))
+    return ids, dist
+
+
+# ---------------------------------------------------------------- gate
+
+def finger_gate_param_count(in_dim: int, hidden: int) -> int:
+    return int(L.load().finger_gate_param_count(in_dim, hidden))
+
+
+def finger_gate_attach(tables: Tables, weights, in_dim: int, hidden: int, eps_gate: float) -> None:
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+    L.check(L.load().finger_gate_attach(tables.handle, w.ctypes.data, in_dim, hidden, float(eps_gate)))
+
+
+def finger_mlp_forward(weights: torch.Tensor, in_dim: int, hidden: int, x: torch.Tensor,
+                       y: torch.Tensor | None = None) -> torch.Tensor:
+    if y is None:
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    L.check(L.load().finger_mlp_forward(weights.data_ptr(), in_dim, hidden, x.data_ptr(),
+                                        x.shape[0], y.data_ptr(), _stream()))
+    return y
+
+
+def finger_mlp_backward(weights: torch.Tensor, in_dim: int, hidden: int, x: torch.Tensor,
+                        target: torch.Tensor, grad: torch.Tensor | None = None,
+                        loss: torch.Tensor | None = None):
+    if grad is None:
+        grad = torch.empty_like(weights)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    L.check(L.load().finger_mlp_backward(weights.data_ptr(), in_dim, hidden, x.data_ptr(),
+                                         target.data_ptr(), x.shape[0], grad.data_ptr(),
+                                         loss.data_ptr(), _stream()))
+    return grad, loss
+
+
+def finger_adam_step(weights, grad, m1, m2, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
+    L.check(L.load().finger_adam_step(weights.data_ptr(), grad.data_ptr(), m1.data_ptr(),
+                                      m2.data_ptr(), weights.numel(), lr, beta1, beta2, eps,
+                                      step, _stream()))

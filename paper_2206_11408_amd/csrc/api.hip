@@ -1,0 +1,706 @@
+// C ABI of libfinger: argument checking, handle lifetime, workspace layout
+// and the order of kernel launches.  Every entry point returns a status and
+// records a message for finger_last_error(); no exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/finger.h"
+#include "internal.h"
+
+using finger::Tables;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return FINGER_OK;
+}
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) return fail(FINGER_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+// Allocation with an injectable failure (FINGER_FAULT_INJECT=alloc makes
+// every allocation fail, to test the error path).
+int dev_alloc(void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (bytes == 0) return FINGER_OK;
+  const char* fi = std::getenv("FINGER_FAULT_INJECT");
+  if (fi != nullptr && std::strcmp(fi, "alloc") == 0)
+    return fail(FINGER_ENOMEM, "allocation of %zu bytes for %s failed (injected)", bytes, what);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(FINGER_ENOMEM, "allocation of %zu bytes for %s failed: %s", bytes, what,
+                hipGetErrorString(e));
+  }
+  return FINGER_OK;
+}
+
+int check_device(int* dev_out) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return fail(FINGER_ENODEV, "no HIP device available");
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(FINGER_ENODEV, "device %d is %s; this library is built for gfx950", dev,
+                prop.gcnArchName);
+  if (dev_out) *dev_out = dev;
+  return FINGER_OK;
+}
+
+int cu_count() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+void free_tables(Tables* t) {
+  if (t == nullptr) return;
+  void* dev_ptrs[] = {t->data_owned, t->P, t->cc, t->pc, t->alpha, t->rho, t->codes, t->scale,
+                      t->piv_ids, t->qprep_B, t->qprep_Bnorm, t->samples, t->xy, t->gate_w,
+                      t->gate_b};
+  for (void* p : dev_ptrs)
+    if (p) (void)hipFree(p);
+  std::free(t->P64_host);
+  std::free(t->eig_host);
+  delete t;
+}
+
+struct Guard {  // frees a half-built handle on error paths
+  Tables* t;
+  ~Guard() { free_tables(t); }
+};
+
+template <typename T>
+struct DevBuf {  // scoped temporary device buffer
+  T* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* finger_last_error(void) { return g_err.c_str(); }
+
+void finger_build_params_init(finger_build_params* p) {
+  if (p == nullptr) return;
+  std::memset(p, 0, sizeof(*p));
+  p->rank = 0;
+  p->code_type = FINGER_CODE_F32;
+  p->metric = FINGER_L2;
+  p->sigma_mode = FINGER_SIGMA_STD;
+  p->n_samples = 0;
+  p->seed = 0;
+  p->pivots = nullptr;
+  p->n_pivots = 0;
+  p->dm_override = 0;
+}
+
+void finger_search_params_init(finger_search_params* p) {
+  if (p == nullptr) return;
+  std::memset(p, 0, sizeof(*p));
+  p->mode = FINGER_MODE_PLAIN;
+  p->k = 10;
+  p->ef = 64;
+  p->entry = 0;
+  p->warmup = 5;
+  p->k_max = 0;
+  p->ef_max = 0;
+  p->persistent = 0;
+}
+
+int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* graph,
+                        int32_t max_degree, const finger_build_params* p, finger_tables** out,
+                        void* stream) {
+  using namespace finger;
+  if (out == nullptr) return fail(FINGER_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (p == nullptr) return fail(FINGER_EINVAL, "params is NULL");
+  if (data == nullptr) return fail(FINGER_EINVAL, "data is NULL");
+  if (graph == nullptr) return fail(FINGER_EINVAL, "graph is NULL");
+  if (n <= 0 || n >= (int64_t)1 << 31) return fail(FINGER_EINVAL, "n = %lld out of range [1, 2^31)", (long long)n);
+  if (m <= 0 || m > kMaxDim || m % 4 != 0)
+    return fail(FINGER_EINVAL, "m = %d must be a multiple of 4 in [4, %d]", m, kMaxDim);
+  if ((reinterpret_cast<uintptr_t>(data) & 15u) != 0) return fail(FINGER_EINVAL, "data must be 16-byte aligned");
+  if (max_degree < 1 || max_degree > kMaxDegree)
+    return fail(FINGER_EINVAL, "max_degree = %d out of range [1, %d]", max_degree, kMaxDegree);
+  if (p->rank < 0 || p->rank > m || p->rank > kMaxRank)
+    return fail(FINGER_EINVAL, "rank = %d out of range [0, min(m, %d)]", p->rank, kMaxRank);
+  if (p->code_type < FINGER_CODE_F32 || p->code_type > FINGER_CODE_FP8E4M3)
+    return fail(FINGER_EINVAL, "unknown code_type %d", p->code_type);
+  if (p->metric != FINGER_L2 && p->metric != FINGER_ANGULAR)
+    return fail(FINGER_EINVAL, "unknown metric %d", p->metric);
+  if (p->sigma_mode != FINGER_SIGMA_STD && p->sigma_mode != FINGER_SIGMA_VARIANCE)
+    return fail(FINGER_EINVAL, "unknown sigma_mode %d", p->sigma_mode);
+  if (p->n_pivots < 0 || p->n_pivots > 65536) return fail(FINGER_EINVAL, "n_pivots = %d out of range", p->n_pivots);
+  if (p->n_pivots > 0 && p->pivots == nullptr) return fail(FINGER_EINVAL, "pivots is NULL with n_pivots > 0");
+  if (p->dm_override && !(p->dm[3] >= 0)) return fail(FINGER_EINVAL, "dm override sigma_hat must be >= 0");
+  int dev = 0;
+  int st = check_device(&dev);
+  if (st != FINGER_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  Tables* t = new (std::nothrow) Tables();
+  if (t == nullptr) return fail(FINGER_ENOMEM, "host allocation failed");
+  Guard guard{t};
+  t->device = dev;
+  t->n = n;
+  t->m = m;
+  t->r = p->rank;
+  t->deg = max_degree;
+  t->code_type = p->code_type;
+  t->metric = p->metric;
+  t->sigma_mode = p->sigma_mode;
+  t->graph = graph;
+  const int rpad = (t->r + 15) / 16 * 16;
+
+  // graph and pivot checks
+  DevBuf<int32_t> bad;
+  if ((st = dev_alloc(reinterpret_cast<void**>(&bad.p), 8, "flags")) != FINGER_OK) return st;
+  HIPCHK(hipMemsetAsync(bad.p, 0, 8, s));
+  HIPCHK(launch_validate_graph(graph, n, max_degree, bad.p, s));
+  if (p->n_pivots > 0) HIPCHK(launch_check_ids(p->pivots, p->n_pivots, n, bad.p + 1, s));
+  int32_t hbad[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(hbad, bad.p, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hbad[0] != 0)
+    return fail(FINGER_EINVAL, "graph: %d rows have an id out of range, a self loop, a repeated id or a gap before -1 padding", hbad[0]);
+  if (hbad[1] != 0) return fail(FINGER_EINVAL, "pivots: %d ids out of range", hbad[1]);
+
+  // the points the search reads
+  if (t->metric == FINGER_ANGULAR) {
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->data_owned), (size_t)n * m * 4, "normalized data")) != FINGER_OK) return st;
+    HIPCHK(launch_normalize_rows(data, n, m, t->data_owned, s));
+    t->data = t->data_owned;
+  } else {
+    t->data = data;
+  }
+  if ((st = dev_alloc(reinterpret_cast<void**>(&t->cc), (size_t)n * 4, "node norms")) != FINGER_OK) return st;
+  HIPCHK(launch_row_norms(t->data, n, m, t->cc, s));
+
+  if (t->r > 0) {
+    // ---- Algorithm 2: samples, residuals, basis, distribution matching
+    const int64_t ns_req = p->n_samples > 0 ? std::min<int64_t>(p->n_samples, n)
+                                            : std::min<int64_t>(n, kDefaultSamples);
+    DevBuf<int32_t> raw;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&raw.p), (size_t)ns_req * 12, "samples")) != FINGER_OK) return st;
+    HIPCHK(launch_sample_pairs(graph, n, max_degree, ns_req, p->seed, raw.p, s));
+    std::vector<int32_t> hs((size_t)ns_req * 3);
+    HIPCHK(hipMemcpyAsync(hs.data(), raw.p, hs.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int32_t> kept;
+    kept.reserve(hs.size());
+    for (int64_t i = 0; i < ns_req; ++i)
+      if (hs[3 * i] >= 0) kept.insert(kept.end(), {hs[3 * i], hs[3 * i + 1], hs[3 * i + 2]});
+    const int64_t ns = (int64_t)kept.size() / 3;
+    if (ns < 2) return fail(FINGER_EINVAL, "fewer than 2 usable samples (nodes need >= 2 neighbours)");
+    t->nsamp = ns;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->samples), kept.size() * 4, "samples")) != FINGER_OK) return st;
+    HIPCHK(hipMemcpyAsync(t->samples, kept.data(), kept.size() * 4, hipMemcpyHostToDevice, s));
+    DevBuf<double> res;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&res.p), (size_t)ns * m * 16, "residuals")) != FINGER_OK) return st;
+    double* res1 = res.p;
+    double* res2 = res.p + (size_t)ns * m;
+    HIPCHK(launch_residuals_f64(t->data, m, t->samples, ns, res1, res2, s));
+    const int parts = gram_parts(ns, m);
+    DevBuf<double> gram;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&gram.p), (size_t)(parts + 1) * m * m * 8, "gram")) != FINGER_OK) return st;
+    HIPCHK(launch_gram_f64(res1, ns, m, gram.p, s));
+    std::vector<double> M((size_t)m * m);
+    HIPCHK(hipMemcpyAsync(M.data(), gram.p, M.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    t->eig_host = static_cast<double*>(std::malloc((size_t)m * 8));
+    std::vector<double> V((size_t)m * m);
+    t->P64_host = static_cast<double*>(std::malloc((size_t)t->r * m * 8));
+    if (!t->eig_host || !t->P64_host) return fail(FINGER_ENOMEM, "host allocation failed");
+    eigh_jacobi(M.data(), m, t->eig_host, V.data());
+    std::memcpy(t->P64_host, V.data(), (size_t)t->r * m * 8);
+    DevBuf<double> P64d;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&P64d.p), (size_t)t->r * m * 8, "basis")) != FINGER_OK) return st;
+    HIPCHK(hipMemcpyAsync(P64d.p, t->P64_host, (size_t)t->r * m * 8, hipMemcpyHostToDevice, s));
+    // P in float, rows padded to rpad with zeros
+    std::vector<float> P32((size_t)rpad * m, 0.f);
+    for (int i = 0; i < t->r; ++i)
+      for (int k = 0; k < m; ++k) P32[(size_t)i * m + k] = (float)t->P64_host[(size_t)i * m + k];
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->P), P32.size() * 4, "basis")) != FINGER_OK) return st;
+    HIPCHK(hipMemcpyAsync(t->P, P32.data(), P32.size() * 4, hipMemcpyHostToDevice, s));
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->xy), (size_t)ns * 16, "cosines")) != FINGER_OK) return st;
+    HIPCHK(launch_pair_cosines(res1, res2, ns, m, P64d.p, t->r, t->xy, s));
+    DevBuf<double> sums;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&sums.p), 6 * 8, "sums")) != FINGER_OK) return st;
+    double hsum[6];
+    HIPCHK(launch_dm_sums(t->xy, ns, 0, 0, 0, 0, sums.p, s));
+    HIPCHK(hipMemcpyAsync(hsum, sums.p, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double mu = hsum[0] / ns, mu_hat = hsum[1] / ns;
+    HIPCHK(launch_dm_sums(t->xy, ns, mu, mu_hat, 0, 1, sums.p, s));
+    HIPCHK(hipMemcpyAsync(hsum, sums.p, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double var = hsum[0] / ns, var_hat = hsum[1] / ns;
+    double sigma, sigma_hat;
+    if (t->sigma_mode == FINGER_SIGMA_STD) {
+      sigma = std::sqrt(var);
+      sigma_hat = std::sqrt(var_hat);
+    } else {
+      sigma = var;
+      sigma_hat = var_hat;
+    }
+    const double scale = sigma_hat > 0 ? sigma / sigma_hat : 1.0;
+    HIPCHK(launch_dm_sums(t->xy, ns, mu, mu_hat, scale, 2, sums.p, s));
+    HIPCHK(hipMemcpyAsync(hsum, sums.p, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    t->mu = mu;
+    t->sigma = sigma;
+    t->mu_hat = mu_hat;
+    t->sigma_hat = sigma_hat;
+    t->eps = hsum[0] / ns;
+    if (p->dm_override) {
+      t->mu = p->dm[0];
+      t->sigma = p->dm[1];
+      t->mu_hat = p->dm[2];
+      t->sigma_hat = p->dm[3];
+      t->eps = p->dm[4];
+    }
+    // ---- node table (Supplementary G): P c for every node
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->pc), (size_t)n * rpad * 4, "node table")) != FINGER_OK) return st;
+    HIPCHK(launch_gemm_nt(t->data, n, t->P, rpad, m, t->pc, rpad, s));
+    // ---- edge table: alpha, rho, u per slot
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->alpha), (size_t)n * max_degree * 4, "edge alpha")) != FINGER_OK) return st;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->rho), (size_t)n * max_degree * 4, "edge rho")) != FINGER_OK) return st;
+    const size_t esz = t->code_type == FINGER_CODE_F32 ? 4 : (t->code_type == FINGER_CODE_BF16 ? 2 : 1);
+    t->code_bytes = (size_t)n * max_degree * rpad * esz;
+    if ((st = dev_alloc(&t->codes, t->code_bytes, "edge codes")) != FINGER_OK) return st;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->scale), (size_t)n * 4, "code scales")) != FINGER_OK) return st;
+    HIPCHK(launch_edge_codes(*t, s));
+  }
+
+  // ---- query-prep operand: P rows (padded to whole 64-column tiles), then pivots
+  t->npiv = p->n_pivots;
+  const int rcols = (rpad + 63) / 64 * 64;
+  const int cols = rcols + (t->npiv + 63) / 64 * 64;
+  t->qprep_cols = cols;
+  if (cols > 0) {
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->qprep_B), (size_t)cols * m * 4, "query-prep operand")) != FINGER_OK) return st;
+    if ((st = dev_alloc(reinterpret_cast<void**>(&t->qprep_Bnorm), (size_t)cols * 4, "query-prep norms")) != FINGER_OK) return st;
+    HIPCHK(hipMemsetAsync(t->qprep_B, 0, (size_t)cols * m * 4, s));
+    if (t->r > 0) HIPCHK(hipMemcpyAsync(t->qprep_B, t->P, (size_t)rpad * m * 4, hipMemcpyDeviceToDevice, s));
+    if (t->npiv > 0) {
+      if ((st = dev_alloc(reinterpret_cast<void**>(&t->piv_ids), (size_t)t->npiv * 4, "pivots")) != FINGER_OK) return st;
+      HIPCHK(hipMemcpyAsync(t->piv_ids, p->pivots, (size_t)t->npiv * 4, hipMemcpyDeviceToDevice, s));
+      HIPCHK(launch_gather_rows(t->data, m, t->piv_ids, t->npiv, t->qprep_B + (size_t)rcols * m, s));
+    }
+    HIPCHK(launch_row_norms(t->qprep_B, cols, m, t->qprep_Bnorm, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  guard.t = nullptr;
+  *out = reinterpret_cast<finger_tables*>(t);
+  return ok();
+}
+
+void finger_free_tables(finger_tables* t) { free_tables(reinterpret_cast<Tables*>(t)); }
+
+int finger_tables_info_get(const finger_tables* th, finger_tables_info* info) {
+  if (th == nullptr || info == nullptr) return fail(FINGER_EINVAL, "NULL argument");
+  const Tables* t = reinterpret_cast<const Tables*>(th);
+  std::memset(info, 0, sizeof(*info));
+  info->n = t->n;
+  info->m = t->m;
+  info->rank = t->r;
+  info->max_degree = t->deg;
+  info->code_type = t->code_type;
+  info->metric = t->metric;
+  info->n_pivots = t->npiv;
+  info->n_samples_used = t->nsamp;
+  info->mu = t->mu;
+  info->sigma = t->sigma;
+  info->mu_hat = t->mu_hat;
+  info->sigma_hat = t->sigma_hat;
+  info->eps = t->eps;
+  info->eps_gate = t->eps_gate;
+  info->gate_attached = t->gate;
+  info->edge_table_bytes = t->r > 0 ? (int64_t)(t->code_bytes + (size_t)t->n * t->deg * 8) : 0;
+  return ok();
+}
+
+int finger_tables_read(const finger_tables* th, int32_t which, void* dst, size_t* bytes) {
+  if (th == nullptr || bytes == nullptr) return fail(FINGER_EINVAL, "NULL argument");
+  const Tables* t = reinterpret_cast<const Tables*>(th);
+  const int rpad = (t->r + 15) / 16 * 16;
+  const void* src = nullptr;
+  size_t sz = 0;
+  bool host = false;
+  bool strip = false;  // rows of rpad floats copied as rows of r
+  int64_t rows = 0;
+  switch (which) {
+    case FINGER_T_P_F64: src = t->P64_host; sz = (size_t)t->r * t->m * 8; host = true; break;
+    case FINGER_T_EIGVALS: src = t->eig_host; sz = t->r > 0 ? (size_t)t->m * 8 : 0; host = true; break;
+    case FINGER_T_P_F32: src = t->P; sz = (size_t)t->r * t->m * 4; break;
+    case FINGER_T_NODE_CC: src = t->cc; sz = (size_t)t->n * 4; break;
+    case FINGER_T_NODE_PC: src = t->pc; sz = (size_t)t->n * t->r * 4; strip = true; rows = t->n; break;
+    case FINGER_T_EDGE_ALPHA: src = t->alpha; sz = t->r > 0 ? (size_t)t->n * t->deg * 4 : 0; break;
+    case FINGER_T_EDGE_RHO: src = t->rho; sz = t->r > 0 ? (size_t)t->n * t->deg * 4 : 0; break;
+    case FINGER_T_EDGE_CODES: src = t->codes; sz = t->code_bytes; break;
+    case FINGER_T_EDGE_SCALE: src = t->scale; sz = t->r > 0 ? (size_t)t->n * 4 : 0; break;
+    case FINGER_T_SAMPLES: src = t->samples; sz = (size_t)t->nsamp * 12; break;
+    case FINGER_T_XY: src = t->xy; sz = (size_t)t->nsamp * 16; break;
+    default: return fail(FINGER_EINVAL, "unknown table selector %d", which);
+  }
+  if (dst == nullptr) {
+    *bytes = sz;
+    return ok();
+  }
+  if (*bytes < sz) {
+    const size_t cap = *bytes;
+    *bytes = sz;
+    return fail(FINGER_EOVERFLOW, "table needs %zu bytes, buffer has %zu", sz, cap);
+  }
+  *bytes = sz;
+  if (sz == 0) return ok();
+  if (host) {
+    std::memcpy(dst, src, sz);
+  } else if (strip && rpad != t->r) {
+    HIPCHK(hipMemcpy2D(dst, (size_t)t->r * 4, src, (size_t)rpad * 4, (size_t)t->r * 4, (size_t)rows,
+                       hipMemcpyDeviceToHost));
+  } else {
+    HIPCHK(hipMemcpy(dst, src, sz, hipMemcpyDeviceToHost));
+  }
+  return ok();
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- search
+
+namespace {
+
+struct Plan {
+  int ef_max, vis_cap, waves, lds;
+  size_t off_qq, off_pq, off_ent, off_queue, off_qscr, off_spill, total;
+};
+
+int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan* pl) {
+  using namespace finger;
+  if (p->mode < FINGER_MODE_PLAIN || p->mode > FINGER_MODE_GATED)
+    return fail(FINGER_EINVAL, "unknown mode %d", p->mode);
+  if (p->mode != FINGER_MODE_PLAIN && t->r == 0)
+    return fail(FINGER_EINVAL, "FINGER modes need a handle built with rank > 0");
+  if (p->mode == FINGER_MODE_GATED && !t->gate)
+    return fail(FINGER_EINVAL, "gated mode needs finger_gate_attach first");
+  if (nq < 0) return fail(FINGER_EINVAL, "nq < 0");
+  const bool perq = p->k_per_query != nullptr || p->ef_per_query != nullptr;
+  if (p->k_per_query == nullptr && (p->k < 1 || p->k > t->n))
+    return fail(FINGER_EINVAL, "k = %d out of range [1, n]", p->k);
+  if (p->ef_per_query == nullptr && p->ef < 1) return fail(FINGER_EINVAL, "ef = %d < 1", p->ef);
+  const int kmax_needed = p->k_per_query == nullptr ? p->k : 1;
+  if (p->k_max < kmax_needed) return fail(FINGER_EINVAL, "k_max = %d < k = %d", p->k_max, p->k);
+  if (p->entry < -1 || p->entry >= t->n) return fail(FINGER_EINVAL, "entry = %d out of range", p->entry);
+  if (p->entry == -1 && t->npiv == 0) return fail(FINGER_EINVAL, "entry = -1 needs pivots in the tables");
+  int ef_max = p->ef_max;
+  if (perq) {
+    if (ef_max < 1) return fail(FINGER_EINVAL, "ef_max must be set with per-query k or ef");
+  } else {
+    const int need = std::max(p->ef, p->k);
+    if (ef_max < need) ef_max = need;
+  }
+  if (ef_max > kMaxEf) return fail(FINGER_EOVERFLOW, "ef_max = %d exceeds %d", ef_max, kMaxEf);
+  int vis_cap = p->visited_capacity;
+  if (vis_cap == 0) vis_cap = std::min(8192, std::max(1024, next_pow2(24 * ef_max)));
+  if (vis_cap < 256 || (vis_cap & (vis_cap - 1)) != 0)
+    return fail(FINGER_EINVAL, "visited_capacity = %d must be a power of two >= 256", vis_cap);
+  const int gate_h = p->mode == FINGER_MODE_GATED ? t->gate_h : 0;
+  const int gate_in = p->mode == FINGER_MODE_GATED ? t->gate_in : 0;
+  const int lds_wave = search_lds_bytes(ef_max, vis_cap, t->r, 0, gate_in);
+  const int lds_shared = search_lds_bytes(0, 0, t->r, gate_h, gate_in) - search_lds_bytes(0, 0, t->r, 0, 0);
+  const int lds_limit = 160 * 1024;
+  const int wpb = p->mode == FINGER_MODE_GATED ? 4 : 1;
+  if (lds_shared + wpb * lds_wave > lds_limit)
+    return fail(FINGER_EOVERFLOW, "per-wave LDS of %d bytes (ef_max %d, visited %d) exceeds the CU budget", lds_wave, ef_max, vis_cap);
+  int per_cu = p->waves_per_cu;
+  const int lds_fit = (lds_limit / (lds_shared + wpb * lds_wave)) * wpb;
+  if (per_cu <= 0) per_cu = std::min(16, lds_fit);
+  if (per_cu > 32) return fail(FINGER_EINVAL, "waves_per_cu = %d > 32", per_cu);
+  per_cu = std::min(per_cu, lds_fit);
+  int waves = per_cu * cu_count();
+  if (nq < waves) waves = (int)std::max<int64_t>(nq, 1);
+  waves = (waves + wpb - 1) / wpb * wpb;
+  const int rpad = (t->r + 15) / 16 * 16;
+  size_t off = 0;
+  pl->off_qq = off;  off += align256((size_t)nq * 4);
+  pl->off_pq = off;  off += align256((size_t)nq * rpad * 4);
+  pl->off_ent = off; off += align256((size_t)nq * 4);
+  pl->off_queue = off; off += 256;
+  pl->off_qscr = off; off += align256(query_prep_scratch_bytes(*t, nq));
+  pl->off_spill = off; off += align256((size_t)waves * kSpillSlots * 4);
+  pl->total = off;
+  pl->ef_max = ef_max;
+  pl->vis_cap = vis_cap;
+  pl->waves = waves;
+  pl->lds = lds_wave;
+  return FINGER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int finger_search_workspace_size(const finger_tables* th, int64_t nq, const finger_search_params* p,
+                                 size_t* bytes) {
+  if (th == nullptr || p == nullptr || bytes == nullptr) return fail(FINGER_EINVAL, "NULL argument");
+  Plan pl;
+  int st = plan_search(reinterpret_cast<const Tables*>(th), nq, p, &pl);
+  if (st != FINGER_OK) return st;
+  *bytes = pl.total;
+  return ok();
+}
+
+int finger_search(const finger_tables* th, const float* queries, int64_t nq,
+                  const finger_search_params* p, int32_t* out_ids, float* out_dist,
+                  int32_t* out_counters, void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace finger;
+  if (th == nullptr || p == nullptr) return fail(FINGER_EINVAL, "NULL handle or params");
+  const Tables* t = reinterpret_cast<const Tables*>(th);
+  Plan pl;
+  int st = plan_search(t, nq, p, &pl);
+  if (st != FINGER_OK) return st;
+  if (nq == 0) return ok();
+  if (queries == nullptr || out_ids == nullptr || out_dist == nullptr)
+    return fail(FINGER_EINVAL, "queries/out_ids/out_dist is NULL");
+  if ((reinterpret_cast<uintptr_t>(queries) & 15u) != 0) return fail(FINGER_EINVAL, "queries must be 16-byte aligned");
+  if (workspace == nullptr || workspace_bytes < pl.total)
+    return fail(FINGER_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, pl.total);
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(FINGER_EINVAL, "workspace must be 256-byte aligned");
+  if (p->log_features != nullptr && (p->mode != FINGER_MODE_FINGER || p->log_targets == nullptr || p->log_count == nullptr))
+    return fail(FINGER_EINVAL, "feature logging needs mode FINGER, log_targets and log_count");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  float* qq = reinterpret_cast<float*>(ws + pl.off_qq);
+  float* pq = reinterpret_cast<float*>(ws + pl.off_pq);
+  int32_t* ent = reinterpret_cast<int32_t*>(ws + pl.off_ent);
+  int32_t* queue = reinterpret_cast<int32_t*>(ws + pl.off_queue);
+  float* qscr = reinterpret_cast<float*>(ws + pl.off_qscr);
+  int32_t* spill = reinterpret_cast<int32_t*>(ws + pl.off_spill);
+  HIPCHK(hipMemsetAsync(queue, 0, 4, s));
+  HIPCHK(hipMemsetAsync(spill, 0xFF, (size_t)pl.waves * kSpillSlots * 4, s));
+  const bool need_prep = p->mode != FINGER_MODE_PLAIN || p->entry == -1;
+  if (need_prep) HIPCHK(launch_query_prep(*t, queries, nq, qq, pq, p->entry == -1 ? ent : nullptr, qscr, s));
+  SearchLaunch L{};
+  L.queries = queries;
+  L.nq = nq;
+  L.mode = p->mode;
+  L.k_all = p->k;
+  L.ef_all = p->ef;
+  L.k_max = p->k_max;
+  L.ef_max = pl.ef_max;
+  L.entry = p->entry;
+  L.warmup = p->warmup < 0 ? 5 : p->warmup;
+  L.kq = p->k_per_query;
+  L.efq = p->ef_per_query;
+  L.qq = qq;
+  L.pq = pq;
+  L.entries = p->entry == -1 ? ent : nullptr;
+  L.out_ids = out_ids;
+  L.out_dist = out_dist;
+  L.counters = out_counters;
+  L.queue = queue;
+  L.spill = spill;
+  L.spill_slots_per_wave = kSpillSlots;
+  L.vis_cap = pl.vis_cap;
+  L.waves = pl.waves;
+  L.persistent = p->persistent;
+  L.log_x = p->log_features;
+  L.log_y = p->log_targets;
+  L.log_cap = p->log_capacity;
+  L.log_count = p->log_count;
+  HIPCHK(launch_search(*t, L, s));
+  return ok();
+}
+
+int finger_estimate_edges(const finger_tables* th, const float* queries, int64_t nq,
+                          const int32_t* q_index, const int32_t* centers, const int32_t* slots,
+                          int64_t n_items, float* out_est, float* out_t_hat, void* stream) {
+  using namespace finger;
+  if (th == nullptr) return fail(FINGER_EINVAL, "NULL handle");
+  const Tables* t = reinterpret_cast<const Tables*>(th);
+  if (t->r == 0) return fail(FINGER_EINVAL, "rank-0 handle has no estimate");
+  if (n_items < 0 || nq < 0) return fail(FINGER_EINVAL, "negative size");
+  if (n_items == 0) return ok();
+  if (!queries || !q_index || !centers || !slots || !out_est || !out_t_hat)
+    return fail(FINGER_EINVAL, "NULL pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int rpad = (t->r + 15) / 16 * 16;
+  DevBuf<float> buf;
+  int st = dev_alloc(reinterpret_cast<void**>(&buf.p), (size_t)nq * (rpad + 1) * 4 + 256, "estimate scratch");
+  if (st != FINGER_OK) return st;
+  Tables tq = *t;
+  tq.npiv = 0;  // Pq and |q|^2 only
+  float* qq = buf.p;
+  float* pq = buf.p + (nq + 63) / 64 * 64;
+  HIPCHK(launch_query_prep(tq, queries, nq, qq, pq, nullptr, nullptr, s));
+  HIPCHK(launch_estimate_edges(*t, queries, qq, pq, q_index, centers, slots, n_items, out_est, out_t_hat, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return ok();
+}
+
+int finger_exact_knn_workspace_size(int64_t n, int32_t m, int64_t nq, int32_t k, size_t* bytes) {
+  if (bytes == nullptr) return fail(FINGER_EINVAL, "bytes is NULL");
+  if (n <= 0 || m <= 0 || m % 4 != 0 || nq < 0 || k < 1 || k > 128 || k > n)
+    return fail(FINGER_EINVAL, "bad sizes (n=%lld m=%d nq=%lld k=%d)", (long long)n, m, (long long)nq, k);
+  *bytes = finger::exact_knn_ws_bytes(n, m, nq, k) + align256((size_t)(n + nq) * m * 4);
+  return ok();
+}
+
+int finger_exact_knn(const float* data, int64_t n, int32_t m, const float* queries, int64_t nq,
+                     int32_t k, int32_t metric, int32_t* out_ids, float* out_dist, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+  using namespace finger;
+  size_t need = 0;
+  int st = finger_exact_knn_workspace_size(n, m, nq, k, &need);
+  if (st != FINGER_OK) return st;
+  if (metric != FINGER_L2 && metric != FINGER_ANGULAR) return fail(FINGER_EINVAL, "unknown metric %d", metric);
+  if (nq == 0) return ok();
+  if (!data || !queries || !out_ids || !out_dist) return fail(FINGER_EINVAL, "NULL pointer");
+  if (((reinterpret_cast<uintptr_t>(data) | reinterpret_cast<uintptr_t>(queries)) & 15u) != 0)
+    return fail(FINGER_EINVAL, "data and queries must be 16-byte aligned");
+  if (workspace == nullptr || workspace_bytes < need)
+    return fail(FINGER_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(FINGER_EINVAL, "workspace must be 256-byte aligned");
+  st = check_device(nullptr);
+  if (st != FINGER_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const float* X = data;
+  const float* Q = queries;
+  char* rest = ws + align256((size_t)(n + nq) * m * 4);
+  if (metric == FINGER_ANGULAR) {
+    float* Xn = reinterpret_cast<float*>(ws);
+    float* Qn = Xn + (size_t)n * m;
+    HIPCHK(launch_normalize_rows(data, n, m, Xn, s));
+    HIPCHK(launch_normalize_rows(queries, nq, m, Qn, s));
+    X = Xn;
+    Q = Qn;
+  }
+  HIPCHK(launch_exact_knn(X, n, m, Q, nq, k, metric, out_ids, out_dist, rest, s));
+  return ok();
+}
+
+// ------------------------------------------------------------------ gate
+
+int64_t finger_gate_param_count(int32_t in_dim, int32_t hidden) {
+  if (in_dim < 1 || hidden < 1) return 0;
+  return (int64_t)hidden * in_dim + (int64_t)hidden * hidden + 3 * (int64_t)hidden + 1;
+}
+
+int finger_gate_attach(finger_tables* th, const float* weights, int32_t in_dim, int32_t hidden,
+                       double eps_gate) {
+  using namespace finger;
+  if (th == nullptr || weights == nullptr) return fail(FINGER_EINVAL, "NULL argument");
+  Tables* t = reinterpret_cast<Tables*>(th);
+  if (t->r == 0) return fail(FINGER_EINVAL, "rank-0 handle cannot take a gate");
+  if (in_dim != FINGER_GATE_FEATURES(t->r))
+    return fail(FINGER_EINVAL, "in_dim = %d, expected 2r+4 = %d", in_dim, FINGER_GATE_FEATURES(t->r));
+  if (hidden < 1 || hidden > 64) return fail(FINGER_EINVAL, "hidden = %d out of range [1, 64]", hidden);
+  const int64_t P = finger_gate_param_count(in_dim, hidden);
+  DevBuf<float> wd;
+  int st = dev_alloc(reinterpret_cast<void**>(&wd.p), (size_t)P * 4, "gate weights");
+  if (st != FINGER_OK) return st;
+  HIPCHK(hipMemcpy(wd.p, weights, (size_t)P * 4, hipMemcpyHostToDevice));
+  const int64_t nw = (int64_t)hidden * in_dim + (int64_t)hidden * hidden + hidden;
+  uint16_t* wbf = nullptr;
+  float* b = nullptr;
+  if ((st = dev_alloc(reinterpret_cast<void**>(&wbf), (size_t)nw * 2, "gate bf16 weights")) != FINGER_OK) return st;
+  if ((st = dev_alloc(reinterpret_cast<void**>(&b), (size_t)(2 * hidden + 1) * 4, "gate biases")) != FINGER_OK) {
+    (void)hipFree(wbf);
+    return st;
+  }
+  hipError_t e = launch_pack_gate(wd.p, in_dim, hidden, wbf, b, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(wbf);
+    (void)hipFree(b);
+    return fail(FINGER_EDEVICE, "packing gate weights: %s", hipGetErrorString(e));
+  }
+  if (t->gate_w) (void)hipFree(t->gate_w);
+  if (t->gate_b) (void)hipFree(t->gate_b);
+  t->gate_w = wbf;
+  t->gate_b = b;
+  t->gate_in = in_dim;
+  t->gate_h = hidden;
+  t->eps_gate = eps_gate;
+  t->gate = 1;
+  return ok();
+}
+
+int finger_mlp_forward(const float* weights, int32_t in_dim, int32_t hidden, const float* x,
+                       int64_t batch, float* y, void* stream) {
+  if (!weights || !x || !y) return fail(FINGER_EINVAL, "NULL pointer");
+  if (in_dim < 1 || hidden < 1 || hidden > 64 || batch < 0) return fail(FINGER_EINVAL, "bad sizes");
+  HIPCHK(finger::launch_mlp_forward(weights, in_dim, hidden, x, batch, y, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+int finger_mlp_backward(const float* weights, int32_t in_dim, int32_t hidden, const float* x,
+                        const float* target, int64_t batch, float* grad, float* loss, void* stream) {
+  if (!weights || !x || !target || !grad) return fail(FINGER_EINVAL, "NULL pointer");
+  if (in_dim < 1 || in_dim > 260 || hidden < 1 || hidden > 64 || batch < 1)
+    return fail(FINGER_EINVAL, "bad sizes (in_dim <= 260, hidden <= 64, batch >= 1)");
+  HIPCHK(finger::launch_mlp_backward(weights, in_dim, hidden, x, target, batch, grad, loss,
+                                     static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+int finger_adam_step(float* weights, const float* grad, float* m1, float* m2, int64_t count,
+                     float lr, float beta1, float beta2, float eps, int32_t step, void* stream) {
+  if (!weights || !grad || !m1 || !m2) return fail(FINGER_EINVAL, "NULL pointer");
+  if (count < 0 || step < 1) return fail(FINGER_EINVAL, "count < 0 or step < 1");
+  if (count == 0) return ok();
+  HIPCHK(finger::launch_adam(weights, grad, m1, m2, count, lr, beta1, beta2, eps, step,
+                             static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal declarations of libfinger: the handle layout and the kernel
+// launchers each .hip file provides to the C ABI layer (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/finger.h"
+
+namespace finger {
+
+// Visited set: LDS open-addressing table per query wave, spilling to a
+// per-wave global table in the workspace when a probe run gets long.
+constexpr int kSpillSlots = 8192;      // global spill entries per wave slot
+constexpr int kMaxDegree = 64;
+constexpr int kMaxEf = 1024;
+constexpr int kMaxRank = 256;
+constexpr int kMaxDim = 2048;
+constexpr int kDefaultSamples = 100000;
+
+struct Tables {
+  int device = 0;
+  int64_t n = 0;
+  int32_t m = 0, r = 0, deg = 0, code_type = 0, metric = 0, sigma_mode = 0;
+  const float* data = nullptr;     // points the search reads (borrowed, or data_owned)
+  float* data_owned = nullptr;     // normalized copy for FINGER_ANGULAR
+  const int32_t* graph = nullptr;  // borrowed
+  // basis
+  double* P64_host = nullptr;      // [r][m]
+  double* eig_host = nullptr;      // [m]
+  float* P = nullptr;              // [r][m]
+  // node table
+  float* cc = nullptr;             // [n]
+  float* pc = nullptr;             // [n][r]
+  // edge table
+  float* alpha = nullptr;          // [n][deg]
+  float* rho = nullptr;            // [n][deg]
+  void* codes = nullptr;           // [n][deg][r] (f32, bf16 or fp8)
+  float* scale = nullptr;          // [n]
+  size_t code_bytes = 0;
+  // pivots: rows r.. of qprep_B hold the pivot vectors, rows 0..r-1 hold P
+  int32_t npiv = 0;
+  int32_t* piv_ids = nullptr;      // [npiv]
+  float* qprep_B = nullptr;        // [(r + npiv) rounded up to 64][m]
+  float* qprep_Bnorm = nullptr;    // [(r + npiv) rounded up to 64]  (|row|^2)
+  int32_t qprep_cols = 0;          // r + npiv rounded up to 64
+  // distribution matching constants
+  double mu = 0, sigma = 1, mu_hat = 0, sigma_hat = 1, eps = 0;
+  // build samples kept for inspection
+  int64_t nsamp = 0;
+  int32_t* samples = nullptr;      // [nsamp][3]
+  double* xy = nullptr;            // [nsamp][2]
+  // learned gate
+  int gate = 0;
+  int32_t gate_in = 0, gate_h = 0;
+  double eps_gate = 0;
+  uint16_t* gate_w = nullptr;      // bf16 weights, layout of finger_gate_attach
+  float* gate_b = nullptr;         // float biases b1 [H], b2 [H], b3 [1]
+};
+
+// ------------------------------------------------------------ launchers
+// Each returns hipSuccess or the launch error.
+
+// C[i][j] = sum_k A[i][k] B[j][k] (fp32 MFMA), A [rows][K], B [cols][K];
+// epilogue modes below.  rows/cols any size, K % 4 == 0.
+enum GemmEpi { GEMM_STORE = 0 };
+hipError_t launch_gemm_nt(const float* A, int64_t rows, const float* B, int64_t cols, int K,
+                          float* C, int64_t ldc, hipStream_t s);
+
+// query preparation: qq[i] = |q_i|^2, Pq[i][0..r) = P q_i, and (if npiv > 0)
+// entries[i] = nearest pivot id by exact squared distance
+hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float* qq, float* Pq,
+                             int32_t* entries, float* scratch, hipStream_t s);
+size_t query_prep_scratch_bytes(const Tables& t, int64_t nq);
+
+struct SearchLaunch {
+  const float* queries;
+  int64_t nq;
+  int mode;
+  int k_all, ef_all, k_max, ef_max, entry, warmup;
+  const int32_t* kq;
+  const int32_t* efq;
+  const float* qq;
+  const float* pq;
+  const int32_t* entries;
+  int32_t* out_ids;
+  float* out_dist;
+  int32_t* counters;
+  int32_t* queue;
+  int32_t* spill;
+  int spill_slots_per_wave;
+  int vis_cap;
+  int waves;        // grid size in waves
+  int persistent;
+  float* log_x;
+  float* log_y;
+  int64_t log_cap;
+  int64_t* log_count;
+};
+hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s);
+int search_lds_bytes(int ef_max, int vis_cap, int r, int gate_h, int gate_in);
+
+hipError_t launch_estimate_edges(const Tables& t, const float* Q, const float* qq,
+                                 const float* Pq, const int32_t* qi, const int32_t* ci,
+                                 const int32_t* si, int64_t items, float* est, float* that,
+                                 hipStream_t s);
+
+// table build
+hipError_t launch_validate_graph(const int32_t* graph, int64_t n, int deg, int32_t* bad,
+                                 hipStream_t s);
+hipError_t launch_sample_pairs(const int32_t* graph, int64_t n, int deg, int64_t ns,
+                               uint64_t seed, int32_t* samples, hipStream_t s);
+hipError_t launch_residuals_f64(const float* data, int m, const int32_t* samples, int64_t ns,
+                                double* res1, double* res2, hipStream_t s);
+int gram_parts(int64_t ns, int m);
+hipError_t launch_gram_f64(const double* R, int64_t ns, int m, double* M, hipStream_t s);
+hipError_t launch_pair_cosines(const double* res1, const double* res2, int64_t ns, int m,
+                               const double* P64, int r, double* xy, hipStream_t s);
+hipError_t launch_dm_sums(const double* xy, int64_t ns, double mu, double mu_hat,
+                          double scale, int stage, double* out, hipStream_t s);
+hipError_t launch_row_norms(const float* X, int64_t n, int m, float* out, hipStream_t s);
+hipError_t launch_edge_codes(const Tables& t, hipStream_t s);
+hipError_t launch_normalize_rows(const float* X, int64_t n, int m, float* Y, hipStream_t s);
+hipError_t launch_gather_rows(const float* X, int m, const int32_t* ids, int64_t cnt, float* Y,
+                              hipStream_t s);
+hipError_t launch_check_ids(const int32_t* ids, int64_t cnt, int64_t n, int32_t* bad,
+                            hipStream_t s);
+
+// exact kNN
+size_t exact_knn_ws_bytes(int64_t n, int m, int64_t nq, int k);
+hipError_t launch_exact_knn(const float* data, int64_t n, int m, const float* Q, int64_t nq,
+                            int k, int metric, int32_t* ids, float* dist, void* ws,
+                            hipStream_t s);
+
+// gate
+hipError_t launch_mlp_forward(const float* w, int in, int H, const float* x, int64_t B, float* y,
+                              hipStream_t s);
+hipError_t launch_mlp_backward(const float* w, int in, int H, const float* x, const float* tgt,
+                               int64_t B, float* grad, float* loss, hipStream_t s);
+hipError_t launch_adam(float* w, const float* g, float* m1, float* m2, int64_t cnt, float lr,
+                       float b1, float b2, float eps, int step, hipStream_t s);
+hipError_t launch_pack_gate(const float* w_dev, int in, int H, uint16_t* wbf, float* b,
+                            hipStream_t s);
+
+// host symmetric eigensolver (cyclic Jacobi), eigenvalues descending,
+// eigenvectors as rows of V [m][m]
+void eigh_jacobi(const double* A, int m, double* evals, double* V);
+
+}  // namespace finger

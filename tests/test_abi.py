@@ -1,0 +1,161 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point include/finger.h declares, the ctypes structures match the C layout,
+and argument errors are reported before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2206_11408_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "finger.h")
+
+
+def _declared():
+    with open(HEADER) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"FINGER_API\s+[\w\s\*]+?\b(finger_\w+)\s*\(", txt)))
+
+
+def test_header_declares_what_binding_lists():
+    assert set(_declared()) == set(L.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (finger_\w+)", out))
+    for name in _declared():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_struct_layout_matches_header():
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "finger.h"
+#define P(s, f) printf(#s "." #f " %zu\n", offsetof(s, f))
+int main(void) {
+  printf("build %zu\nsearch %zu\ninfo %zu\n", sizeof(finger_build_params),
+         sizeof(finger_search_params), sizeof(finger_tables_info));
+  P(finger_build_params, n_samples); P(finger_build_params, pivots); P(finger_build_params, dm);
+  P(finger_search_params, k_per_query); P(finger_search_params, ef_max);
+  P(finger_search_params, log_features); P(finger_search_params, log_count);
+  P(finger_tables_info, n_samples_used); P(finger_tables_info, mu); P(finger_tables_info, gate_attached);
+  P(finger_tables_info, edge_table_bytes);
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    vals = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    assert int(vals["build"]) == C.sizeof(L.BuildParams)
+    assert int(vals["search"]) == C.sizeof(L.SearchParams)
+    assert int(vals["info"]) == C.sizeof(L.TablesInfo)
+    for key, v in vals.items():
+        if "." not in key:
+            continue
+        sname, field = key.split(".")
+        cls = {"finger_build_params": L.BuildParams, "finger_search_params": L.SearchParams,
+               "finger_tables_info": L.TablesInfo}[sname]
+        assert getattr(cls, field).offset == int(v), key
+
+
+def _bp(**kw):
+    p = L.BuildParams()
+    L.load().finger_build_params_init(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("n,m,deg,rank,code,metric,msg", [
+    (0, 32, 8, 0, 0, 0, "n = 0"),
+    (10, 30, 8, 0, 0, 0, "multiple of 4"),
+    (10, 4096, 8, 0, 0, 0, "multiple of 4"),
+    (10, 32, 0, 0, 0, 0, "max_degree"),
+    (10, 32, 65, 0, 0, 0, "max_degree"),
+    (10, 32, 8, 33, 0, 0, "rank"),
+    (10, 32, 8, -1, 0, 0, "rank"),
+    (10, 32, 8, 8, 7, 0, "code_type"),
+    (10, 32, 8, 8, 0, 5, "metric"),
+])
+def test_build_rejects_bad_arguments(n, m, deg, rank, code, metric, msg):
+    lib = L.load()
+    p = _bp(rank=rank, code_type=code, metric=metric)
+    h = C.c_void_p()
+    fake = 1 << 20  # never dereferenced: validation happens first
+    st = lib.finger_build_tables(fake, n, m, fake, deg, C.byref(p), C.byref(h), None)
+    assert st == L.FINGER_EINVAL
+    assert msg in lib.finger_last_error().decode()
+    assert h.value is None
+
+
+def test_build_rejects_null_pointers():
+    lib = L.load()
+    p = _bp()
+    h = C.c_void_p()
+    assert lib.finger_build_tables(None, 10, 32, 1 << 20, 8, C.byref(p), C.byref(h), None) == L.FINGER_EINVAL
+    assert "data is NULL" in lib.finger_last_error().decode()
+    assert lib.finger_build_tables(1 << 20, 10, 32, None, 8, C.byref(p), C.byref(h), None) == L.FINGER_EINVAL
+    assert lib.finger_build_tables(1 << 20, 10, 32, 1 << 20, 8, None, C.byref(h), None) == L.FINGER_EINVAL
+    assert lib.finger_build_tables(1 << 20, 10, 32, 1 << 20, 8, C.byref(p), None, None) == L.FINGER_EINVAL
+
+
+def test_misaligned_data_rejected():
+    lib = L.load()
+    p = _bp()
+    h = C.c_void_p()
+    assert lib.finger_build_tables((1 << 20) + 4, 10, 32, 1 << 20, 8, C.byref(p), C.byref(h), None) == L.FINGER_EINVAL
+    assert "aligned" in lib.finger_last_error().decode()
+
+
+def test_no_device_reports_enodev():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = L.load()
+    p = _bp()
+    h = C.c_void_p()
+    st = lib.finger_build_tables(1 << 20, 10, 32, 1 << 20, 8, C.byref(p), C.byref(h), None)
+    assert st == L.FINGER_ENODEV
+
+
+def test_exact_knn_workspace_validation():
+    lib = L.load()
+    nb = C.c_size_t(0)
+    assert lib.finger_exact_knn_workspace_size(100, 32, 10, 0, C.byref(nb)) == L.FINGER_EINVAL
+    assert lib.finger_exact_knn_workspace_size(100, 30, 10, 5, C.byref(nb)) == L.FINGER_EINVAL
+    assert lib.finger_exact_knn_workspace_size(100, 32, 10, 129, C.byref(nb)) == L.FINGER_EINVAL
+    assert lib.finger_exact_knn_workspace_size(100, 32, 10, 5, C.byref(nb)) == L.FINGER_OK
+    assert nb.value > 0
+
+
+def test_null_handle_search_calls():
+    lib = L.load()
+    sp = L.SearchParams()
+    lib.finger_search_params_init(C.byref(sp))
+    nb = C.c_size_t(0)
+    assert lib.finger_search_workspace_size(None, 1, C.byref(sp), C.byref(nb)) == L.FINGER_EINVAL
+    assert lib.finger_search(None, None, 0, C.byref(sp), None, None, None, None, 0, None) == L.FINGER_EINVAL
+    info = L.TablesInfo()
+    assert lib.finger_tables_info_get(None, C.byref(info)) == L.FINGER_EINVAL
+    lib.finger_free_tables(None)  # no-op
+
+
+def test_gate_param_count():
+    lib = L.load()
+    # in = 2r + 4 with r = 64, H = 64: 64*132 + 64 + 64*64 + 64 + 64 + 1
+    assert lib.finger_gate_param_count(132, 64) == 12737
+    assert lib.finger_gate_param_count(0, 64) == 0
