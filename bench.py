@@ -1,0 +1,311 @@
+"""Benchmark: queries/s at recall@10 = 0.95, FINGER vs plain greedy search on
+one MI355X, with the search kernel's achieved HBM bandwidth.
+
+Workload (default): n = 1,000,000 points, m = 128, integer features 0..255
+from a 1,000-cluster mixture; graph = exact 16-NN symmetrized and pruned to
+degree 32 with reachability repair; 4,096 pivot entry points; FINGER rank
+r = 64 with fp32 edge codes; 10,000 queries from the same mixture; K = 10.
+All inputs are synthetic and seeded (workloads package).
+
+Flow: build inputs and the exact ground truth (finger_exact_knn), build the
+FINGER tables, sweep ef for both modes to find the smallest ef with
+recall@10 >= 0.95, then time K steps (one step = query preparation + search
+of all queries at that ef) after W warm-up steps.  Prints ONE JSON line on
+stdout; progress goes to stderr.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+EF_SWEEP = (10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 200)
+TARGET_RECALL = 0.95
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(ctr: np.ndarray, m: int, deg: int, r: int, code_bytes: int,
+                      k: int, fp8: bool) -> float:
+    """Bytes the method must move for one launch, summed over its queries:
+    the query, one adjacency row per expansion, one vector per exact
+    distance, c.c and P c per screening expansion, one edge code (plus
+    alpha_d, rho_d, and the per-node scale for FP8) per screened edge, and
+    the K results."""
+    exp, exact, scr, preps = (ctr[:, 0].astype(np.float64), ctr[:, 1].astype(np.float64),
+                              ctr[:, 2].astype(np.float64), ctr[:, 5].astype(np.float64))
+    per_q = (4 * m + exp * 4 * deg + exact * 4 * m + preps * 4 * (r + 1)
+             + scr * (r * code_bytes + 8) + (preps * 4 if fp8 else 0) + 8 * k)
+    return float(per_q.sum())
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("search.hip", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2206_11408_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(mode_name: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current search kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "search_c2_counters.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("workload") != workload:
+        return None
+    ent = rec.get("modes", {}).get(mode_name)
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--clusters", type=int, default=1000)
+    ap.add_argument("--nq", type=int, default=10_000)
+    ap.add_argument("--rank", type=int, default=64)
+    ap.add_argument("--code", choices=("f32", "bf16", "fp8"), default="f32")
+    ap.add_argument("--pivots", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=200,
+                    help="queries of the oracle CPU baseline (0 = skip)")
+    ap.add_argument("--extra-codes", default="",
+                    help="comma list of extra code types to sweep and report (bf16,fp8)")
+    ap.add_argument("--ef-plain", type=int, default=0, help="skip the plain sweep, use this ef")
+    ap.add_argument("--ef-finger", type=int, default=0, help="skip the FINGER sweep, use this ef")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (the reference kernel for HBM counters)")
+    a = ap.parse_args()
+
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the per-shard search on a "
+              "single MI355X (see DESIGN.md for how it would shard). Use --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2206_11408_amd import _lib as L
+    from paper_2206_11408_amd import api
+    from workloads import SPECS, build_graph, make_points, pick_pivots
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    code_of = {"f32": (L.CODE_F32, 4), "bf16": (L.CODE_BF16, 2), "fp8": (L.CODE_FP8E4M3, 1)}
+
+    # ------------------------------------------------------------ inputs
+    spec = SPECS["c2"].scaled(n=a.n, n_centers=a.clusters, nq=a.nq)
+    t0 = time.time()
+    data, queries = make_points(spec)
+    log(f"points n={a.n} m={spec.m} nq={a.nq} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    G, medoid, gstats = build_graph(data, knn_k=spec.knn_k, max_degree=spec.max_degree, device="cuda")
+    log(f"graph in {time.time() - t0:.1f}s: {gstats}")
+    piv = pick_pivots(a.n, a.pivots, spec.seed)
+    d_data = torch.as_tensor(data, device=dev)
+    d_q = torch.as_tensor(queries, device=dev)
+    d_G = torch.as_tensor(G, device=dev)
+    t0 = time.time()
+    gt_ids, gt_d = api.finger_exact_knn(d_data, d_q, 10)
+    torch.cuda.synchronize()
+    log(f"ground truth (exact kNN, MFMA) in {time.time() - t0:.2f}s")
+    gt_ids = gt_ids.cpu().numpy()
+    gt_d = gt_d.cpu().numpy()
+
+    def recall(ids, dist):
+        # tie-aware: a returned id also counts if it sits at the 10th distance
+        kth = gt_d[:, 9:10]
+        hit = (ids[:, :10, None] == gt_ids[:, None, :10]).any(2) | ((dist[:, :10] <= kth) & (ids[:, :10] >= 0))
+        return float(hit.mean())
+
+    tables = {}
+
+    def get_tables(code):
+        if code not in tables:
+            t0 = time.time()
+            tables[code] = api.finger_build_tables(d_data, d_G, rank=a.rank, code_type=code_of[code][0],
+                                                   pivots=piv, seed=0)
+            torch.cuda.synchronize()
+            inf = tables[code].info()
+            log(f"FINGER tables r={a.rank} {code} in {time.time() - t0:.1f}s: mu={inf['mu']:.4f} "
+                f"sigma={inf['sigma']:.4f} mu_hat={inf['mu_hat']:.4f} sigma_hat={inf['sigma_hat']:.4f} "
+                f"eps={inf['eps']:.4f} edge bytes={inf['edge_table_bytes'] / 1e9:.2f} GB")
+        return tables[code]
+
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    kev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for e in ev + kev:   # torch creates the HIP event on first record
+        e.record()
+    torch.cuda.synchronize()
+
+    def run(tab, mode, ef, out=None, time_kernel=False):
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1)
+        if time_kernel:
+            p.kernel_events[0] = kev[0].cuda_event
+            p.kernel_events[1] = kev[1].cuda_event
+        return api.finger_search(tab, d_q, p, out=out)
+
+    def sweep(tab, mode):
+        res = []
+        for ef in EF_SWEEP:
+            run(tab, mode, ef)
+            torch.cuda.synchronize()
+            ev[0].record()
+            ids, dist, ctr = run(tab, mode, ef)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1])
+            rc = recall(ids.cpu().numpy(), dist.cpu().numpy())
+            c = ctr.cpu().numpy()
+            res.append(dict(ef=ef, recall=rc, ms=ms, qps=a.nq / ms * 1e3,
+                            exact=float(c[:, 1].mean()), screened=float(c[:, 2].mean()),
+                            skipped=float(c[:, 3].mean()), expansions=float(c[:, 0].mean()),
+                            status_bad=int((c[:, 6] != 0).sum())))
+            log(f"  mode={mode} ef={ef:4d} recall={rc:.4f} {ms:7.3f} ms  qps={a.nq / ms * 1e3:,.0f} "
+                f"exp={res[-1]['expansions']:.1f} exact={res[-1]['exact']:.1f} "
+                f"scr={res[-1]['screened']:.1f} skip={res[-1]['skipped']:.1f}")
+            if rc >= TARGET_RECALL + 0.01 and ef >= 16:
+                break
+        ok = [r for r in res if r["recall"] >= TARGET_RECALL]
+        return res, (min(ok, key=lambda r: r["ef"]) if ok else max(res, key=lambda r: r["recall"]))
+
+    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8):
+        nq = a.nq
+        out = (torch.empty((nq, 10), dtype=torch.int32, device=dev),
+               torch.empty((nq, 10), dtype=torch.float32, device=dev),
+               torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
+        for _ in range(warmup):
+            run(tab, mode, ef, out)
+        torch.cuda.synchronize()
+        kms = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run(tab, mode, ef, out, time_kernel=True)
+            kev[1].synchronize()
+            kms.append(kev[0].elapsed_time(kev[1]))
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        ids, dist, ctr = (x.cpu().numpy() for x in out)
+        B = algorithmic_bytes(ctr, spec.m, spec.max_degree, a.rank if mode else 0, code_bytes, 10, fp8)
+        kavg = float(np.mean(kms))
+        return dict(ef=ef, qps=nq * steps / total, ms_per_step=total / steps * 1e3,
+                    kernel_ms=kavg, kernel_ms_min=float(np.min(kms)), alg_bytes=B,
+                    alg_gbs=B / (kavg * 1e-3) / 1e9, recall=recall(ids, dist),
+                    exact=float(ctr[:, 1].mean()), skipped=float(ctr[:, 3].mean()),
+                    screened=float(ctr[:, 2].mean()))
+
+    tabF = get_tables(a.code)
+    if a.copy_probe:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 1 GiB device-to-device copy done")
+    if a.ef_plain:
+        op_p = {"ef": a.ef_plain, "recall": float("nan")}
+    else:
+        log("sweep plain")
+        sw_p, op_p = sweep(tabF, L.MODE_PLAIN)
+    if a.ef_finger:
+        op_f = {"ef": a.ef_finger, "recall": float("nan")}
+    else:
+        log("sweep finger")
+        sw_f, op_f = sweep(tabF, L.MODE_FINGER)
+    log(f"operating points: plain ef={op_p['ef']} recall={op_p['recall']:.4f}; "
+        f"finger ef={op_f['ef']} recall={op_f['recall']:.4f}")
+
+    cb, fp8 = code_of[a.code][1], a.code == "fp8"
+    # timed region: plain baseline, then FINGER (the metric)
+    tp = timed(tabF, L.MODE_PLAIN, op_p["ef"], a.steps, a.warmup, cb, fp8)
+    log(f"plain  timed: {tp}")
+    tf = timed(tabF, L.MODE_FINGER, op_f["ef"], a.steps, a.warmup, cb, fp8)
+    log(f"finger timed: {tf}")
+
+    extra = {}
+    for code in [c for c in a.extra_codes.split(",") if c]:
+        tab = get_tables(code)
+        sw, op = sweep(tab, L.MODE_FINGER)
+        tx = timed(tab, L.MODE_FINGER, op["ef"], a.steps, a.warmup, code_of[code][1], code == "fp8")
+        extra[code] = dict(ef=op["ef"], recall=tx["recall"], qps=tx["qps"], kernel_ms=tx["kernel_ms"],
+                           alg_gbs=tx["alg_gbs"], speedup_vs_plain=tx["qps"] / tp["qps"])
+        log(f"finger {code} timed: {tx}")
+
+    # ------------------------------------------------------ CPU baseline
+    cpu = None
+    if a.cpu_sample > 0:
+        from oracle.build import build as oracle_build
+        from oracle.search import pivot_entries, search_batch
+        t0 = time.time()
+        orc = oracle_build(data, G, a.rank, n_samples=100_000, seed=0)
+        log(f"oracle tables in {time.time() - t0:.1f}s")
+        qs = queries[:a.cpu_sample]
+        ent = pivot_entries(qs, data, piv)
+        t0 = time.process_time()
+        w0 = time.perf_counter()
+        search_batch(data, G, qs, ent, op_f["ef"], 10, mode="finger", tables=orc)
+        wall = time.perf_counter() - w0
+        cpu = {"value": round(a.cpu_sample / wall, 3), "unit": "queries/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{a.cpu_sample} of the {a.nq} queries, FINGER mode at ef={op_f['ef']}, "
+                         f"float64 single-threaded oracle (entry selection included, table build excluded)"}
+        log(f"cpu oracle: {cpu}")
+
+    workload = (f"c2: n={a.n} m={spec.m} int 0-255, {a.clusters}-cluster mixture, 16-NN sym pruned "
+                f"deg 32, {a.pivots} pivots, r={a.rank} {a.code} codes, nq={a.nq}, K=10")
+    traffic = measured_traffic("finger", workload)
+    roof = {"bound": "hbm", "achieved": round(tf["alg_gbs"], 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(tf["alg_gbs"] / PEAK_HBM_GBS, 4),
+            "traffic": traffic, "kernel": "k_search (FINGER mode)",
+            "kernel_ms": round(tf["kernel_ms"], 4), "alg_bytes_per_launch": round(tf["alg_bytes"])}
+    line = {
+        "metric": "queries/sec at recall@10=0.95 (FINGER search, 1 MI355X)",
+        "value": round(tf["qps"], 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(tf["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "ef_finger": op_f["ef"], "ef_plain": op_p["ef"],
+                   "recall_finger": round(tf["recall"], 4), "recall_plain": round(tp["recall"], 4)},
+        "plain_qps": round(tp["qps"], 1),
+        "speedup_vs_plain": round(tf["qps"] / tp["qps"], 4),
+        "plain_roofline": {"achieved": round(tp["alg_gbs"], 1), "frac": round(tp["alg_gbs"] / PEAK_HBM_GBS, 4),
+                           "kernel_ms": round(tp["kernel_ms"], 4)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if extra:
+        line["extra_codes"] = extra
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -79,9 +79,12 @@ enum {
   FINGER_CTR_SCREENED = 2,   /* neighbours screened by the estimate */
   FINGER_CTR_SKIPPED = 3,    /* screened neighbours whose estimate exceeded ub */
   FINGER_CTR_VISITED = 4,    /* |V| at the end */
-  FINGER_CTR_STATUS = 5,     /* 0 = ok; 1 = visited-set capacity reached (search
-                                stopped early; raise visited_capacity) */
-  FINGER_NCOUNTERS = 6
+  FINGER_CTR_PREPS = 5,      /* expansions that screened (each reads c.c and P c) */
+  FINGER_CTR_STATUS = 6,     /* 0 = ok; bit 0: visited-set capacity reached (the
+                                remaining neighbours were treated as visited;
+                                raise visited_capacity); bit 1: ef_eff clipped
+                                to ef_max */
+  FINGER_NCOUNTERS = 7
 };
 
 /* ---------------------------------------------------------------- build */
@@ -213,6 +216,10 @@ typedef struct finger_search_params {
   float* log_targets;
   int64_t log_capacity;
   int64_t* log_count;
+  /* Optional hipEvent_t pair recorded on `stream` immediately before and
+   * after the search kernel (not the query preparation), for timing the
+   * kernel alone; NULL = none. */
+  void* kernel_events[2];
 } finger_search_params;
 
 FINGER_API void finger_search_params_init(finger_search_params* p /* host */);

@@ -41,7 +41,7 @@ import numpy as np
 from .estimate import estimate as finger_estimate
 from .knn import sqdist
 
-COUNTER_NAMES = ("expansions", "exact", "screened", "skipped", "visited")
+COUNTER_NAMES = ("expansions", "exact", "screened", "skipped", "visited", "preps")
 
 
 class _TopList:
@@ -124,6 +124,7 @@ def search(data: np.ndarray, graph: np.ndarray, q: np.ndarray, entry: int,
                 ub2 = T.worst()[0]
                 est = est_of(cur, new, ub2)
                 cnt["screened"] += len(new)
+                cnt["preps"] += 1
                 keep = est <= ub2
                 cnt["skipped"] += int((~keep).sum())
                 if ub2 > 0:
@@ -176,7 +177,7 @@ def pivot_entries(queries: np.ndarray, data: np.ndarray, pivots: np.ndarray) -> 
 def search_batch(data, graph, queries, entries, ef, k, **kw):
     """``search`` over many queries.  ``entries`` is one id or one per query;
     ``ef``/``k`` are scalars or per-query sequences.  Returns (ids [nq, kmax],
-    d2 [nq, kmax], counters int64 [nq, 5], margins [nq])."""
+    d2 [nq, kmax], counters int64 [nq, 6] in COUNTER_NAMES order, margins [nq])."""
     queries = np.atleast_2d(queries)
     nq = queries.shape[0]
     ks = np.broadcast_to(np.asarray(k), (nq,))

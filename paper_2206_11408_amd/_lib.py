@@ -22,8 +22,8 @@ L2, ANGULAR = 0, 1
 CODE_F32, CODE_BF16, CODE_FP8E4M3 = 0, 1, 2
 MODE_PLAIN, MODE_FINGER, MODE_GATED = 0, 1, 2
 SIGMA_STD, SIGMA_VARIANCE = 0, 1
-NCOUNTERS = 6
-COUNTER_NAMES = ("expansions", "exact", "screened", "skipped", "visited", "status")
+NCOUNTERS = 7
+COUNTER_NAMES = ("expansions", "exact", "screened", "skipped", "visited", "preps", "status")
 
 (T_P_F64, T_EIGVALS, T_P_F32, T_NODE_CC, T_NODE_PC, T_EDGE_ALPHA, T_EDGE_RHO,
  T_EDGE_CODES, T_EDGE_SCALE, T_SAMPLES, T_XY) = range(11)
@@ -56,6 +56,7 @@ class SearchParams(C.Structure):
         ("visited_capacity", C.c_int32),
         ("log_features", C.c_void_p), ("log_targets", C.c_void_p),
         ("log_capacity", C.c_int64), ("log_count", C.c_void_p),
+        ("kernel_events", C.c_void_p * 2),
     ]
 
 

@@ -556,7 +556,11 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.log_y = p->log_targets;
   L.log_cap = p->log_capacity;
   L.log_count = p->log_count;
+  hipEvent_t ev0 = static_cast<hipEvent_t>(p->kernel_events[0]);
+  hipEvent_t ev1 = static_cast<hipEvent_t>(p->kernel_events[1]);
+  if (ev0) HIPCHK(hipEventRecord(ev0, s));
   HIPCHK(launch_search(*t, L, s));
+  if (ev1) HIPCHK(hipEventRecord(ev1, s));
   return ok();
 }
 

@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
     }
     wave_lds_sync();
     int tn = 1;
-    int n_exp = 0, n_exact = 1, n_scr = 0, n_skip = 0, n_vis = 1;
+    int n_exp = 0, n_exact = 1, n_scr = 0, n_skip = 0, n_vis = 1, n_prep = 0;
 
     while (true) {
       float* TD = tD[cur_buf];
@@ -444,6 +444,7 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
       if constexpr (MODE != FINGER_MODE_PLAIN) {
         if (screening) {
           n_scr += S;
+          ++n_prep;
           logging = (MODE == FINGER_MODE_FINGER) && a.log_x != nullptr;
           if (logging) {
             unsigned long long got = 0;
@@ -615,7 +616,8 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
       c[2] = n_scr;
       c[3] = n_skip;
       c[4] = n_vis;
-      c[5] = status | (any_over ? 1 : 0);
+      c[5] = n_prep;
+      c[6] = status | (any_over ? 1 : 0);
     }
     if (any_spill) {
       for (int i = l; i < a.spill_slots; i += 64) spill[i] = -1;

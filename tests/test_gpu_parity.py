@@ -77,8 +77,8 @@ def test_plain_search_parity_c1(api, ef):
     assert same.mean() >= 0.999
     np.testing.assert_allclose(dist[same], od[same], rtol=1e-5, atol=1e-6)
     # on queries that took the same path the counters agree exactly
-    np.testing.assert_array_equal(ctr[same][:, :5], oc[same])
-    assert (ctr[:, 5] == 0).all()
+    np.testing.assert_array_equal(ctr[same][:, :6], oc[same])
+    assert (ctr[:, 6] == 0).all()
 
 
 def test_plain_search_parity_integer_pivots(api):
@@ -90,7 +90,7 @@ def test_plain_search_parity_integer_pivots(api):
     oi, od, oc, _ = search_batch(data, G, qs, ent, 32, 10)
     np.testing.assert_array_equal(ids.cpu().numpy(), oi)
     np.testing.assert_array_equal(dist.cpu().numpy().astype(np.float64), od)
-    np.testing.assert_array_equal(ctr.cpu().numpy()[:, :5], oc)
+    np.testing.assert_array_equal(ctr.cpu().numpy()[:, :6], oc)
 
 
 def test_tables_against_oracle(api):
@@ -201,7 +201,7 @@ def test_finger_search_parity_margin_aware(api, r, ef):
          f"{same[safe].mean():.4f} of them, {same.mean():.4f} overall")
     assert safe.mean() > 0.5
     assert same[safe].all()
-    np.testing.assert_array_equal(ctr[safe][:, :5], oc[safe])
+    np.testing.assert_array_equal(ctr[safe][:, :6], oc[safe])
     # returned distances are exact for the returned ids
     for i in range(0, qs.shape[0], 7):
         ok = ids[i] >= 0
