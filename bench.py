@@ -90,7 +90,9 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=200,
                     help="queries of the oracle CPU baseline (0 = skip)")
     ap.add_argument("--extra-codes", default="",
-                    help="comma list of extra code types to sweep and report (bf16,fp8)")
+                    help="comma list of extra FINGER variants to sweep and report: "
+                         "code[:pf|:nopf] with code in f32,bf16,fp8 (pf = edge codes requested "
+                         "with the adjacency row)")
     ap.add_argument("--ef-plain", type=int, default=0, help="skip the plain sweep, use this ef")
     ap.add_argument("--ef-finger", type=int, default=0, help="skip the FINGER sweep, use this ef")
     ap.add_argument("--copy-probe", action="store_true",
@@ -159,20 +161,20 @@ def main() -> int:
         e.record()
     torch.cuda.synchronize()
 
-    def run(tab, mode, ef, out=None, time_kernel=False):
-        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1)
+    def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0):
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1, code_prefetch=prefetch)
         if time_kernel:
             p.kernel_events[0] = kev[0].cuda_event
             p.kernel_events[1] = kev[1].cuda_event
         return api.finger_search(tab, d_q, p, out=out)
 
-    def sweep(tab, mode):
+    def sweep(tab, mode, prefetch=0):
         res = []
         for ef in EF_SWEEP:
-            run(tab, mode, ef)
+            run(tab, mode, ef, prefetch=prefetch)
             torch.cuda.synchronize()
             ev[0].record()
-            ids, dist, ctr = run(tab, mode, ef)
+            ids, dist, ctr = run(tab, mode, ef, prefetch=prefetch)
             ev[1].record()
             torch.cuda.synchronize()
             ms = ev[0].elapsed_time(ev[1])
@@ -190,18 +192,18 @@ def main() -> int:
         ok = [r for r in res if r["recall"] >= TARGET_RECALL]
         return res, (min(ok, key=lambda r: r["ef"]) if ok else max(res, key=lambda r: r["recall"]))
 
-    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8):
+    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0):
         nq = a.nq
         out = (torch.empty((nq, 10), dtype=torch.int32, device=dev),
                torch.empty((nq, 10), dtype=torch.float32, device=dev),
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
         for _ in range(warmup):
-            run(tab, mode, ef, out)
+            run(tab, mode, ef, out, prefetch=prefetch)
         torch.cuda.synchronize()
         kms = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            run(tab, mode, ef, out, time_kernel=True)
+            run(tab, mode, ef, out, time_kernel=True, prefetch=prefetch)
             kev[1].synchronize()
             kms.append(kev[0].elapsed_time(kev[1]))
         torch.cuda.synchronize()
@@ -244,13 +246,17 @@ def main() -> int:
     log(f"finger timed: {tf}")
 
     extra = {}
-    for code in [c for c in a.extra_codes.split(",") if c]:
+    for variant in [c for c in a.extra_codes.split(",") if c]:
+        code, _, pfs = variant.partition(":")
+        pf = {"pf": 1, "nopf": -1, "": 0}[pfs]
         tab = get_tables(code)
-        sw, op = sweep(tab, L.MODE_FINGER)
-        tx = timed(tab, L.MODE_FINGER, op["ef"], a.steps, a.warmup, code_of[code][1], code == "fp8")
-        extra[code] = dict(ef=op["ef"], recall=tx["recall"], qps=tx["qps"], kernel_ms=tx["kernel_ms"],
-                           alg_gbs=tx["alg_gbs"], speedup_vs_plain=tx["qps"] / tp["qps"])
-        log(f"finger {code} timed: {tx}")
+        sw, op = sweep(tab, L.MODE_FINGER, prefetch=pf)
+        tx = timed(tab, L.MODE_FINGER, op["ef"], a.steps, a.warmup, code_of[code][1], code == "fp8",
+                   prefetch=pf)
+        extra[variant] = dict(ef=op["ef"], recall=round(tx["recall"], 4), qps=round(tx["qps"], 1),
+                              kernel_ms=round(tx["kernel_ms"], 4), alg_gbs=round(tx["alg_gbs"], 1),
+                              speedup_vs_plain=round(tx["qps"] / tp["qps"], 4))
+        log(f"finger {variant} timed: {tx}")
 
     # ------------------------------------------------------ CPU baseline
     cpu = None

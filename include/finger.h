@@ -207,6 +207,11 @@ typedef struct finger_search_params {
   int32_t waves_per_cu;  /* resident query waves per CU; 0 = library default */
   int32_t visited_capacity; /* visited-set slots per query (power of two,
                                >= 256); 0 = default from ef_max */
+  int32_t code_prefetch; /* FINGER mode: 1 = request every slot's edge code
+                            together with the adjacency row (one round trip
+                            fewer, more bytes); -1 = request codes of
+                            unvisited neighbours only; 0 = library default
+                            (prefetch for BF16/FP8 codes) */
   /* Gate-training log (mode FINGER only; NULL = off).  For every screened
    * neighbour the kernel appends one row of FINGER_GATE_FEATURES(r) floats
    * (see finger_gate_attach) to log_features, its exact squared distance

@@ -63,7 +63,7 @@ class Tables:
         L.check(lib.finger_tables_read(self.handle, which, buf.ctypes.data, C.byref(nbytes)))
         inf = self.info()
         n, m, r, deg = inf["n"], inf["m"], inf["rank"], inf["max_degree"]
-        rpad = (r + 15) // 16 * 16
+        rpad = (r + 31) // 32 * 32
         if which in (L.T_P_F64,):
             return buf.view(np.float64).reshape(r, m)
         if which == L.T_EIGVALS:
@@ -133,7 +133,8 @@ def finger_build_tables(data: torch.Tensor, graph: torch.Tensor, rank: int = 0,
 
 def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
                   k_per_query=None, ef_per_query=None, ef_max=0, persistent=0,
-                  waves_per_cu=0, visited_capacity=0, log=None) -> L.SearchParams:
+                  waves_per_cu=0, visited_capacity=0, code_prefetch=0,
+                  log=None) -> L.SearchParams:
     p = L.SearchParams()
     L.load().finger_search_params_init(C.byref(p))
     p.mode, p.k, p.ef, p.entry, p.warmup = mode, k, ef, entry, warmup
@@ -142,6 +143,7 @@ def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
     p.ef_per_query = _ptr(ef_per_query)
     p.ef_max, p.persistent = ef_max, persistent
     p.waves_per_cu, p.visited_capacity = waves_per_cu, visited_capacity
+    p.code_prefetch = code_prefetch
     if log is not None:
         feats, targs, count = log
         p.log_features, p.log_targets = feats.data_ptr(), targs.data_ptr()

@@ -17,6 +17,7 @@
 #include "internal.h"
 
 using finger::Tables;
+using finger::rpad_of;
 
 namespace {
 
@@ -197,7 +198,7 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
   t->metric = p->metric;
   t->sigma_mode = p->sigma_mode;
   t->graph = graph;
-  const int rpad = (t->r + 15) / 16 * 16;
+  const int rpad = rpad_of(t->r);
 
   // graph and pivot checks
   DevBuf<int32_t> bad;
@@ -370,7 +371,7 @@ int finger_tables_info_get(const finger_tables* th, finger_tables_info* info) {
 int finger_tables_read(const finger_tables* th, int32_t which, void* dst, size_t* bytes) {
   if (th == nullptr || bytes == nullptr) return fail(FINGER_EINVAL, "NULL argument");
   const Tables* t = reinterpret_cast<const Tables*>(th);
-  const int rpad = (t->r + 15) / 16 * 16;
+  const int rpad = rpad_of(t->r);
   const void* src = nullptr;
   size_t sz = 0;
   bool host = false;
@@ -419,7 +420,7 @@ int finger_tables_read(const finger_tables* th, int32_t which, void* dst, size_t
 namespace {
 
 struct Plan {
-  int ef_max, vis_cap, waves, lds;
+  int ef_max, vis_cap, waves, lds, spill_slots;
   size_t off_qq, off_pq, off_ent, off_queue, off_qscr, off_spill, total;
 };
 
@@ -450,6 +451,8 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   if (ef_max > kMaxEf) return fail(FINGER_EOVERFLOW, "ef_max = %d exceeds %d", ef_max, kMaxEf);
   int vis_cap = p->visited_capacity;
   if (vis_cap == 0) vis_cap = std::min(8192, std::max(1024, next_pow2(24 * ef_max)));
+  if (p->code_prefetch < -1 || p->code_prefetch > 1)
+    return fail(FINGER_EINVAL, "code_prefetch = %d must be -1, 0 or 1", p->code_prefetch);
   if (vis_cap < 256 || (vis_cap & (vis_cap - 1)) != 0)
     return fail(FINGER_EINVAL, "visited_capacity = %d must be a power of two >= 256", vis_cap);
   const int gate_h = p->mode == FINGER_MODE_GATED ? t->gate_h : 0;
@@ -468,14 +471,16 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   int waves = per_cu * cu_count();
   if (nq < waves) waves = (int)std::max<int64_t>(nq, 1);
   waves = (waves + wpb - 1) / wpb * wpb;
-  const int rpad = (t->r + 15) / 16 * 16;
+  const int rpad = rpad_of(t->r);
   size_t off = 0;
   pl->off_qq = off;  off += align256((size_t)nq * 4);
   pl->off_pq = off;  off += align256((size_t)nq * rpad * 4);
   pl->off_ent = off; off += align256((size_t)nq * 4);
   pl->off_queue = off; off += 256;
   pl->off_qscr = off; off += align256(query_prep_scratch_bytes(*t, nq));
-  pl->off_spill = off; off += align256((size_t)waves * kSpillSlots * 4);
+  const int spill_slots = std::min(16384, std::max(1024, next_pow2(8 * ef_max)));
+  pl->off_spill = off; off += align256((size_t)waves * spill_slots * 4);
+  pl->spill_slots = spill_slots;
   pl->total = off;
   pl->ef_max = ef_max;
   pl->vis_cap = vis_cap;
@@ -525,7 +530,7 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   float* qscr = reinterpret_cast<float*>(ws + pl.off_qscr);
   int32_t* spill = reinterpret_cast<int32_t*>(ws + pl.off_spill);
   HIPCHK(hipMemsetAsync(queue, 0, 4, s));
-  HIPCHK(hipMemsetAsync(spill, 0xFF, (size_t)pl.waves * kSpillSlots * 4, s));
+  HIPCHK(hipMemsetAsync(spill, 0xFF, (size_t)pl.waves * pl.spill_slots * 4, s));
   const bool need_prep = p->mode != FINGER_MODE_PLAIN || p->entry == -1;
   if (need_prep) HIPCHK(launch_query_prep(*t, queries, nq, qq, pq, p->entry == -1 ? ent : nullptr, qscr, s));
   SearchLaunch L{};
@@ -548,10 +553,11 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.counters = out_counters;
   L.queue = queue;
   L.spill = spill;
-  L.spill_slots_per_wave = kSpillSlots;
+  L.spill_slots_per_wave = pl.spill_slots;
   L.vis_cap = pl.vis_cap;
   L.waves = pl.waves;
   L.persistent = p->persistent;
+  L.prefetch = p->code_prefetch > 0 || (p->code_prefetch == 0 && t->code_type != FINGER_CODE_F32);
   L.log_x = p->log_features;
   L.log_y = p->log_targets;
   L.log_cap = p->log_capacity;
@@ -576,7 +582,7 @@ int finger_estimate_edges(const finger_tables* th, const float* queries, int64_t
   if (!queries || !q_index || !centers || !slots || !out_est || !out_t_hat)
     return fail(FINGER_EINVAL, "NULL pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int rpad = (t->r + 15) / 16 * 16;
+  const int rpad = rpad_of(t->r);
   DevBuf<float> buf;
   int st = dev_alloc(reinterpret_cast<void**>(&buf.p), (size_t)nq * (rpad + 1) * 4 + 256, "estimate scratch");
   if (st != FINGER_OK) return st;

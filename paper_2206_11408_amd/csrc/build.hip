@@ -435,7 +435,7 @@ hipError_t launch_gather_rows(const float* X, int m, const int32_t* ids, int64_t
 }
 
 hipError_t launch_edge_codes(const Tables& t, hipStream_t s) {
-  const int rpad = (t.r + 15) / 16 * 16;
+  const int rpad = rpad_of(t.r);
   const int per = t.m + rpad + t.deg * rpad;
   int wpb = (int)(160 * 1024 / (per * (int)sizeof(float)));
   if (wpb > 4) wpb = 4;

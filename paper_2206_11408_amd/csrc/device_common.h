@@ -90,6 +90,13 @@ __device__ __forceinline__ uint64_t bitonic_sort(uint64_t v) {
   return v;
 }
 
+// float -> nearest bfloat16 value (round to nearest even), kept as float
+__device__ __forceinline__ float round_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
 // bf16 -> float
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 

@@ -183,15 +183,24 @@ __global__ void k_adam(float* w, const float* g, float* m1, float* m2, int64_t c
   w[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
+// bf16 weights for the search kernel, transposed so that one lane per
+// hidden unit reads consecutive addresses: W1T [in][H], W2T [H][H], W3 [H]
 __global__ void k_pack_gate(const float* w, int in, int H, uint16_t* wbf, float* b) {
   const Off o = offsets(in, H);
-  const int64_t nw = (int64_t)H * in + (int64_t)H * H + H;
+  const int64_t n1 = (int64_t)H * in, n2 = (int64_t)H * H;
+  const int64_t nw = n1 + n2 + H;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
        i += (int64_t)gridDim.x * blockDim.x) {
     float v;
-    if (i < (int64_t)H * in) v = w[o.w1 + i];
-    else if (i < (int64_t)H * in + (int64_t)H * H) v = w[o.w2 + (i - (int64_t)H * in)];
-    else v = w[o.w3 + (i - (int64_t)H * in - (int64_t)H * H)];
+    if (i < n1) {
+      const int64_t inp = i / H, hid = i % H;  // W1T[inp][hid] = W1[hid][inp]
+      v = w[o.w1 + hid * in + inp];
+    } else if (i < n1 + n2) {
+      const int64_t k = i - n1, inp = k / H, hid = k % H;
+      v = w[o.w2 + hid * H + inp];
+    } else {
+      v = w[o.w3 + (i - n1 - n2)];
+    }
     wbf[i] = (uint16_t)(__float_as_uint(rbf(v)) >> 16);
   }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

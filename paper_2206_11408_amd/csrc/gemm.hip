@@ -239,7 +239,7 @@ size_t query_prep_scratch_bytes(const Tables& t, int64_t nq) {
 hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float* qq, float* Pq,
                              int32_t* entries, float* scratch, hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  const int rpad = (t.r + 15) / 16 * 16;
+  const int rpad = rpad_of(t.r);
   const int rcols = (rpad + BN - 1) / BN * BN;  // P block padded to whole tiles
   const int ntiles = t.npiv > 0 ? (t.npiv + BN - 1) / BN : 0;
   float2* best = reinterpret_cast<float2*>(scratch);

@@ -13,12 +13,15 @@ namespace finger {
 
 // Visited set: LDS open-addressing table per query wave, spilling to a
 // per-wave global table in the workspace when a probe run gets long.
-constexpr int kSpillSlots = 8192;      // global spill entries per wave slot
 constexpr int kMaxDegree = 64;
 constexpr int kMaxEf = 1024;
 constexpr int kMaxRank = 256;
 constexpr int kMaxDim = 2048;
 constexpr int kDefaultSamples = 100000;
+
+// Per-node and per-edge rows of FINGER's projected tables hold r values
+// padded to a multiple of 32 (one 32-element chunk per lane in the search).
+inline int rpad_of(int r) { return (r + 31) / 32 * 32; }
 
 struct Tables {
   int device = 0;
@@ -94,12 +97,14 @@ struct SearchLaunch {
   int vis_cap;
   int waves;        // grid size in waves
   int persistent;
+  int prefetch;     // issue every slot's edge code with the adjacency row
   float* log_x;
   float* log_y;
   int64_t log_cap;
   int64_t* log_count;
 };
 hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s);
+bool search_prefetch_supported(const Tables& t);
 int search_lds_bytes(int ef_max, int vis_cap, int r, int gate_h, int gate_in);
 
 hipError_t launch_estimate_edges(const Tables& t, const float* Q, const float* qq,
