@@ -326,6 +326,19 @@ FINGER_API int finger_exact_knn(const float* data, int64_t n, int32_t m,
 FINGER_API int finger_gate_attach(finger_tables* t, const float* weights /* host */,
                        int32_t in_dim, int32_t hidden, double eps_gate);
 
+/*
+ * finger_gate_targets - training targets from a feature log written by
+ * finger_search: for row i, t_i = cos(q_res, d_res) recovered from the logged
+ * exact squared distance through Eq. 2,
+ *   q_res.d_res = (|q_proj - d_proj|^2 + |q_res|^2 + |d_res|^2 - d2) / 2,
+ * with |q_res|, |d_res| and |q_proj - d_proj|^2 taken from features 2r+1..2r+3
+ * scaled back by the logged bound ub2.  Rows with a zero residual get 0.
+ *   log_features [rows][2r+4], log_targets [rows][2] (d2, ub2), out [rows].
+ * Async.  Errors: EINVAL (NULL pointers, rows < 0, rank < 1).
+ */
+FINGER_API int finger_gate_targets(const float* log_features, const float* log_targets,
+                                   int64_t rows, int32_t rank, float* out, void* stream);
+
 /* Number of floats in the weight layout above. */
 FINGER_API int64_t finger_gate_param_count(int32_t in_dim, int32_t hidden);
 

@@ -14,9 +14,10 @@ readings of the text:
   (the square root of Algorithm 2's quantity).  ``sigma_mode="variance"``
   keeps the literal reading.
 * Basis.  P = U_{1:r}^T from the SVD of D_res (m x N), uncentred
-  (Proposition 3.1).  Only the row space of P matters downstream: every
-  estimate uses cosines of P-projections, unchanged by signs or rotations
-  of P's rows.
+  (Proposition 3.1).  Algorithm 3's estimate depends only on P's row space
+  (cosines of P-projections are unchanged by signs or rotations of P's
+  rows); each row's sign is fixed so that its largest-magnitude entry is
+  positive, which the learned gate's per-coordinate features need.
 * Degenerate vectors.  c.c = 0 gives no projection (alpha = 0); a cosine
   with a zero vector is 0; sigma_hat = 0 makes the scale factor 1.
 * Samples.  One pair per sampled node; N_s = min(n, n_samples) nodes drawn
@@ -60,11 +61,24 @@ def residual_pairs(data: np.ndarray, c: np.ndarray, d: np.ndarray,
     return D - a[:, None] * C, Dp - ap[:, None] * C
 
 
+def canonical_signs(P: np.ndarray) -> np.ndarray:
+    """Flip each row so that its entry of largest magnitude (the first one on
+    ties) is positive.  Singular vectors are defined up to sign; fixing it
+    makes per-coordinate features of P-projections comparable across
+    implementations."""
+    P = P.copy()
+    for i in range(P.shape[0]):
+        j = int(np.argmax(np.abs(P[i])))
+        if P[i, j] < 0:
+            P[i] = -P[i]
+    return P
+
+
 def basis_from_residuals(Dres_rows: np.ndarray, rank: int) -> tuple[np.ndarray, np.ndarray]:
     """Proposition 3.1: the first r left singular vectors of D_res (m x N)
-    as the rows of P.  Returns (P [r, m], singular values)."""
+    as the rows of P (signs canonical).  Returns (P [r, m], singular values)."""
     U, S, _ = np.linalg.svd(Dres_rows.T, full_matrices=False)
-    return U[:, :rank].T.copy(), S
+    return canonical_signs(U[:, :rank].T), S
 
 
 def dm_stats(X: np.ndarray, Y: np.ndarray, sigma_mode: str = "std"):

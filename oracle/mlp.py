@@ -18,6 +18,7 @@ from __future__ import annotations
 import numpy as np
 
 from .build import split
+from .codes import round_bf16
 from .estimate import parts
 
 
@@ -46,14 +47,19 @@ def init_params(in_dim: int, H: int, seed: int = 0) -> np.ndarray:
     return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3, [0.0]])
 
 
-def forward(w, X, in_dim: int, H: int, keep: bool = False):
+def forward(w, X, in_dim: int, H: int, keep: bool = False, bf16_operands: bool = False):
+    """Network output.  With ``bf16_operands`` the weights, the inputs and
+    both hidden layers are rounded to bfloat16 before each product (biases
+    stay exact), the operand precision the library's kernels use; the
+    arithmetic itself stays float64."""
     W1, b1, W2, b2, W3, b3 = unpack(w, in_dim, H)
     X = np.atleast_2d(np.asarray(X, dtype=np.float64))
-    z1 = X @ W1.T + b1
-    h1 = np.maximum(z1, 0)
-    z2 = h1 @ W2.T + b2
-    h2 = np.maximum(z2, 0)
-    y = h2 @ W3 + b3
+    r = round_bf16 if bf16_operands else (lambda a: a)
+    z1 = r(X) @ r(W1).T + b1
+    h1 = r(np.maximum(z1, 0))
+    z2 = h1 @ r(W2).T + b2
+    h2 = r(np.maximum(z2, 0))
+    y = h2 @ r(W3) + b3
     if keep:
         return y, (X, z1, h1, z2, h2)
     return y
@@ -125,10 +131,11 @@ def target_cosine(d2, q_res_norm, d_res_norm, proj):
     return np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
 
 
-def gated_estimate(q, c, D, tables: dict, w, H: int, eps_gate: float, ub2: float) -> np.ndarray:
+def gated_estimate(q, c, D, tables: dict, w, H: int, eps_gate: float, ub2: float,
+                   bf16_operands: bool = True) -> np.ndarray:
     """Eq. 2 with t = f(features) + eps_gate (the gated screen)."""
     P = tables["P"]
     F = edge_features(q, c, D, P, ub2)
-    t = forward(w, F, F.shape[1], H) + eps_gate
+    t = forward(w, F, F.shape[1], H, bf16_operands=bf16_operands) + eps_gate
     p = parts(q, c, D, P)
     return p["proj"] + p["rq"] ** 2 + p["rd"] ** 2 - 2 * p["rq"] * p["rd"] * t

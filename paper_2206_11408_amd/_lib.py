@@ -34,7 +34,7 @@ EXPORTED = (
     "finger_search_workspace_size", "finger_search", "finger_estimate_edges",
     "finger_exact_knn_workspace_size", "finger_exact_knn", "finger_gate_attach",
     "finger_gate_param_count", "finger_mlp_forward", "finger_mlp_backward",
-    "finger_adam_step", "finger_last_error",
+    "finger_adam_step", "finger_gate_targets", "finger_last_error",
 )
 
 
@@ -121,6 +121,8 @@ def load() -> C.CDLL:
     lib.finger_adam_step.restype = C.c_int
     lib.finger_adam_step.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
                                      C.c_float, i32, vp]
+    lib.finger_gate_targets.restype = C.c_int
+    lib.finger_gate_targets.argtypes = [vp, vp, i64, i32, vp, vp]
     _lib = lib
     return lib
 

@@ -149,6 +149,8 @@ def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
         p.log_features, p.log_targets = feats.data_ptr(), targs.data_ptr()
         p.log_capacity = feats.shape[0]
         p.log_count = count.data_ptr()
+    # the struct holds raw device pointers: keep their tensors alive with it
+    p._keep = (k_per_query, ef_per_query, log)
     return p
 
 
@@ -244,6 +246,14 @@ def finger_mlp_backward(weights: torch.Tensor, in_dim: int, hidden: int, x: torc
                                          target.data_ptr(), x.shape[0], grad.data_ptr(),
                                          loss.data_ptr(), _stream()))
     return grad, loss
+
+
+def finger_gate_targets(log_features: torch.Tensor, log_targets: torch.Tensor, rows: int,
+                        rank: int) -> torch.Tensor:
+    out = torch.empty(rows, dtype=torch.float32, device=log_features.device)
+    L.check(L.load().finger_gate_targets(log_features.data_ptr(), log_targets.data_ptr(), rows,
+                                         rank, out.data_ptr(), _stream()))
+    return out
 
 
 def finger_adam_step(weights, grad, m1, m2, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, step=1):

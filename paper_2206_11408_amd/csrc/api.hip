@@ -685,6 +685,15 @@ int finger_gate_attach(finger_tables* th, const float* weights, int32_t in_dim, 
   return ok();
 }
 
+int finger_gate_targets(const float* log_features, const float* log_targets, int64_t rows,
+                        int32_t rank, float* out, void* stream) {
+  if (!log_features || !log_targets || !out) return fail(FINGER_EINVAL, "NULL pointer");
+  if (rows < 0 || rank < 1) return fail(FINGER_EINVAL, "rows < 0 or rank < 1");
+  HIPCHK(finger::launch_gate_targets(log_features, log_targets, rows, rank, out,
+                                     static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
 int finger_mlp_forward(const float* weights, int32_t in_dim, int32_t hidden, const float* x,
                        int64_t batch, float* y, void* stream) {
   if (!weights || !x || !y) return fail(FINGER_EINVAL, "NULL pointer");

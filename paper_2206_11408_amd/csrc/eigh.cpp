@@ -2,7 +2,8 @@
 // method (Golub and Van Loan, "Matrix Computations", the cyclic Jacobi
 // algorithm).  Used once per build on the m x m second-moment matrix of the
 // sampled residuals, whose top-r eigenvectors are the left singular vectors
-// Proposition 3.1 asks for.
+// Proposition 3.1 asks for.  Each eigenvector's sign is fixed so that its
+// largest-magnitude entry is positive.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -75,7 +76,12 @@ void eigh_jacobi(const double* Ain, int m, double* evals, double* Vout) {
   for (int i = 0; i < m; ++i) {
     const int src = order[i];
     evals[i] = A[(size_t)src * m + src];
-    for (int k = 0; k < m; ++k) Vout[(size_t)i * m + k] = V[(size_t)k * m + src];
+    // sign: the entry of largest magnitude (first on ties) is positive
+    int jmax = 0;
+    for (int k = 1; k < m; ++k)
+      if (std::fabs(V[(size_t)k * m + src]) > std::fabs(V[(size_t)jmax * m + src])) jmax = k;
+    const double sgn = V[(size_t)jmax * m + src] < 0 ? -1.0 : 1.0;
+    for (int k = 0; k < m; ++k) Vout[(size_t)i * m + k] = sgn * V[(size_t)k * m + src];
   }
 }
 

@@ -211,7 +211,27 @@ __global__ void k_pack_gate(const float* w, int in, int H, uint16_t* wbf, float*
   if (i == 0) b[2 * H] = w[o.b3];
 }
 
+// cos(q_res, d_res) from a logged row through Eq. 2
+__global__ void k_gate_targets(const float* x, const float* y, int64_t rows, int r, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const float* f = x + i * (int64_t)(2 * r + 4);
+  const float d2 = y[2 * i], ub2 = y[2 * i + 1];
+  const float ub = sqrtf(ub2);
+  const float rq = f[2 * r + 1] * ub, rd = f[2 * r + 2] * ub, proj = f[2 * r + 3] * ub2;
+  const float den = 2.f * rq * rd;
+  out[i] = den > 0.f ? (proj + rq * rq + rd * rd - d2) / den : 0.f;
+}
+
 }  // namespace
+
+hipError_t launch_gate_targets(const float* x, const float* y, int64_t rows, int r, float* out,
+                               hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gate_targets, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, x, y,
+                     rows, r, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_mlp_forward(const float* w, int in, int H, const float* x, int64_t B, float* y,
                               hipStream_t s) {

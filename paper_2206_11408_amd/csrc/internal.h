@@ -146,6 +146,8 @@ hipError_t launch_mlp_backward(const float* w, int in, int H, const float* x, co
                                int64_t B, float* grad, float* loss, hipStream_t s);
 hipError_t launch_adam(float* w, const float* g, float* m1, float* m2, int64_t cnt, float lr,
                        float b1, float b2, float eps, int step, hipStream_t s);
+hipError_t launch_gate_targets(const float* x, const float* y, int64_t rows, int r, float* out,
+                               hipStream_t s);
 hipError_t launch_pack_gate(const float* w_dev, int in, int H, uint16_t* wbf, float* b,
                             hipStream_t s);
 

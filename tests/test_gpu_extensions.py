@@ -1,0 +1,282 @@
+"""GPU tests of the extensions beyond the paper: low-precision edge codes,
+the persistent work-queue launch and its geometry, and the learned gate."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.build import build as oracle_build
+from oracle.codes import quantize_codes
+from oracle.estimate import estimate as oracle_estimate
+from oracle.knn import sqdist
+from oracle.mlp import adam_step, edge_features, forward, gated_estimate, init_params, loss_and_grad
+from oracle.search import pivot_entries, search, search_batch
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    from paper_2206_11408_amd import api as A
+    torch.cuda.init()
+    return A
+
+
+def _t(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _oracle_codes(data, G, P, c, code):
+    """Decoded stored codes of node c's slots in the oracle's basis."""
+    cv = data[c].astype(np.float64)
+    rows = []
+    for d in G[c]:
+        if d < 0:
+            rows.append(np.zeros(P.shape[0]))
+            continue
+        dv = data[d].astype(np.float64)
+        res = dv - (cv @ dv) / (cv @ cv) * cv
+        u = P @ res
+        rows.append(u / np.linalg.norm(u))
+    return quantize_codes(np.array(rows), code)
+
+
+# ---------------------------------------------------------------- codes
+
+@pytest.mark.parametrize("code", ["bf16", "fp8"])
+def test_low_precision_codes_and_estimates(api, code):
+    from paper_2206_11408_amd import _lib as L
+    _say(f"codes {code}: stored values and estimate error vs oracle")
+    data, qs, G, _, _ = helpers.c2_small()
+    ct = {"bf16": L.CODE_BF16, "fp8": L.CODE_FP8E4M3}[code]
+    tab = api.finger_build_tables(_t(data), _t(G), rank=64, code_type=ct, seed=1)
+    orc = oracle_build(data, G, 64, n_samples=100_000, seed=1)
+    P = tab.read(L.T_P_F64)
+    raw = tab.read(L.T_EDGE_CODES)
+    scale = tab.read(L.T_EDGE_SCALE)
+    rng = np.random.default_rng(0)
+    for c in rng.integers(0, data.shape[0], 20):
+        if code == "bf16":
+            dec = (raw[c, :, :64].astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        else:
+            from oracle.codes import e4m3_values
+            dec = e4m3_values()[raw[c, :, :64]] * scale[c]
+        want = _oracle_codes(data, G, orc["P"], c, code)
+        # through the projector (basis signs are free); allow one step of the
+        # format where float32 and float64 inputs round to different neighbours
+        step = 2.0 ** -7 if code == "bf16" else 2.0 ** -3
+        np.testing.assert_allclose(dec @ P, want @ orc["P"], atol=step * 1.01)
+    # estimate error of the quantized screen against the float64 estimate
+    n_items = 300
+    qi = rng.integers(0, qs.shape[0], n_items)
+    ci = rng.integers(0, data.shape[0], n_items)
+    deg = (G >= 0).sum(1)
+    si = np.array([rng.integers(0, deg[c]) for c in ci])
+    est, _ = api.finger_estimate_edges(tab, _t(qs), qi, ci, si)
+    est = est.cpu().numpy().astype(np.float64)
+    exact_est = np.array([oracle_estimate(qs[q], data[c], data[G[c, s]][None], orc)[0]
+                          for q, c, s in zip(qi, ci, si)])
+    quant_est = np.array([oracle_estimate(qs[q], data[c], data[G[c, s]][None], orc,
+                                          codes=_oracle_codes(data, G, orc["P"], c, code)[s][None])[0]
+                          for q, c, s in zip(qi, ci, si)])
+    d2 = np.array([sqdist(qs[q], data[G[c, s]][None])[0] for q, c, s in zip(qi, ci, si)])
+    scale_ = np.maximum(np.abs(exact_est), d2)
+    err_vs_exact = np.abs(est - exact_est) / scale_
+    err_vs_quant = np.abs(est - quant_est) / scale_
+    _say(f"{code}: estimate error vs float64 codes max {err_vs_exact.max():.2e} "
+         f"mean {err_vs_exact.mean():.2e}; vs oracle-quantized codes max {err_vs_quant.max():.2e}")
+    assert np.median(err_vs_quant) < 1e-4
+    assert err_vs_exact.max() < (2e-2 if code == "bf16" else 1e-1)
+
+
+# ------------------------------------------------------ persistent + geometry
+
+def test_persistent_mixed_k_ef_equals_separate_launches(api):
+    _say("persistent launch with K in {1,10,100}, ef in {32..512} vs grouped launches and oracle")
+    import torch
+    data, qs, G, entry, _ = helpers.c1(nq=400)
+    tab = api.finger_build_tables(_t(data), _t(G), rank=0)
+    rng = np.random.default_rng(7)
+    K = rng.choice([1, 10, 100], size=qs.shape[0]).astype(np.int32)
+    EF = rng.choice([32, 64, 128, 256, 512], size=qs.shape[0]).astype(np.int32)
+    p = api.search_params(mode=0, k=100, k_max=100, ef=32, entry=entry, k_per_query=_t(K),
+                          ef_per_query=_t(EF), ef_max=512, persistent=1)
+    ids, dist, ctr = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), p))
+    for k in (1, 10, 100):
+        for ef in (32, 64, 128, 256, 512):
+            sel = np.nonzero((K == k) & (EF == ef))[0]
+            if sel.size == 0:
+                continue
+            a, b, c = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs[sel]), mode=0, k=k, ef=ef,
+                                                                  entry=entry))
+            np.testing.assert_array_equal(ids[sel, :k], a)
+            np.testing.assert_array_equal(dist[sel, :k], b)
+            np.testing.assert_array_equal(ctr[sel], c)
+            assert (ids[sel, k:] == -1).all()
+    oi, od, oc, _ = search_batch(data, G, qs[:120], entry, EF[:120], K[:120])
+    same = [(ids[i, :K[i]] == oi[i, :K[i]]).all() for i in range(120)]
+    assert np.mean(same) >= 0.99
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_results_independent_of_launch_geometry(api, mode):
+    _say(f"geometry invariance mode={mode}")
+    data, qs, G, _, piv = helpers.c2_small()
+    tab = api.finger_build_tables(_t(data), _t(G), rank=64 if mode else 0, pivots=piv)
+    base = dict(mode=mode, k=10, ef=48, entry=-1)
+    ref = [x.cpu().numpy() for x in api.finger_search(tab, _t(qs), **base)]
+    variants = [dict(waves_per_cu=1), dict(waves_per_cu=2, persistent=1), dict(persistent=1),
+                dict(visited_capacity=256), dict(visited_capacity=256, persistent=1, waves_per_cu=3)]
+    if mode:
+        variants += [dict(code_prefetch=1), dict(code_prefetch=-1, persistent=1)]
+    for v in variants:
+        got = [x.cpu().numpy() for x in api.finger_search(tab, _t(qs), **base, **v)]
+        for x, y in zip(ref, got):
+            np.testing.assert_array_equal(x, y, err_msg=str(v))
+
+
+def test_autotuner_picks_a_valid_setting(api, tmp_path):
+    from paper_2206_11408_amd import tune
+    data, qs, G, _, piv = helpers.c2_small()
+    tab = api.finger_build_tables(_t(data), _t(G), rank=64, pivots=piv)
+    base = dict(mode=1, k=10, ef=48, entry=-1)
+    cache = tmp_path / "tune.json"
+    choice = tune.autotune(tab, _t(qs), base, repeats=1, cache_path=str(cache))
+    assert choice["ms"] > 0 and len(choice["all"]) >= 4
+    again = tune.autotune(tab, _t(qs), base, cache_path=str(cache))
+    assert again["waves_per_cu"] == choice["waves_per_cu"]
+    ref = [x.cpu().numpy() for x in api.finger_search(tab, _t(qs), **base)]
+    got = [x.cpu().numpy() for x in api.finger_search(
+        tab, _t(qs), **base, **{k: choice[k] for k in ("waves_per_cu", "persistent", "code_prefetch")})]
+    for x, y in zip(ref, got):
+        np.testing.assert_array_equal(x, y)
+
+
+# ------------------------------------------------------------------ gate
+
+def test_gate_kernels_against_oracle(api):
+    _say("gate forward / backward / Adam vs float64 oracle")
+    import torch
+    rng = np.random.default_rng(11)
+    in_dim, H, B = 132, 64, 1000
+    w = init_params(in_dim, H, seed=2) + rng.normal(size=in_dim * H + H * H + 3 * H + 1) * 0.05
+    X = rng.normal(size=(B, in_dim)) * 0.3
+    t = rng.normal(size=B) * 0.2
+    wd = _t(w.astype(np.float32))
+    Xd = _t(X.astype(np.float32))
+    y = api.finger_mlp_forward(wd, in_dim, H, Xd).cpu().numpy()
+    y_bf = forward(w.astype(np.float32), X.astype(np.float32), in_dim, H, bf16_operands=True)
+    np.testing.assert_allclose(y, y_bf, rtol=1e-4, atol=1e-4)
+    y64 = forward(w, X, in_dim, H)
+    assert np.abs(y - y64).max() / np.abs(y64).max() < 2e-2
+    g, loss = api.finger_mlp_backward(wd, in_dim, H, Xd, _t(t.astype(np.float32)))
+    l64, g64 = loss_and_grad(w, X, t, in_dim, H)
+    g = g.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    _say(f"gradient relative error (bf16 operands vs float64) {rel:.3e}; loss {float(loss.item()):.5f} vs {l64:.5f}")
+    assert rel < 2e-2
+    assert float(loss.item()) == pytest.approx(l64, rel=2e-2)
+    # Adam
+    m1 = torch.zeros_like(wd)
+    m2 = torch.zeros_like(wd)
+    gd = _t(g.astype(np.float32))
+    w2 = wd.clone()
+    for step in (1, 2):
+        api.finger_adam_step(w2, gd, m1, m2, lr=1e-3, step=step)
+    wo, mo1, mo2 = w.astype(np.float32).astype(np.float64), np.zeros_like(w), np.zeros_like(w)
+    for step in (1, 2):
+        wo, mo1, mo2 = adam_step(wo, g.astype(np.float32).astype(np.float64), mo1, mo2, step, lr=1e-3)
+    np.testing.assert_allclose(w2.cpu().numpy(), wo, rtol=1e-5, atol=1e-6)
+
+
+def test_feature_log_matches_oracle_screening(api):
+    _say("gate feature log vs oracle screening records")
+    import torch
+    from paper_2206_11408_amd import gate
+    data, qs, G, _, piv = helpers.c2_small()
+    tab = api.finger_build_tables(_t(data), _t(G), rank=64, pivots=piv, seed=2)
+    orc = oracle_build(data, G, 64, n_samples=100_000, seed=2)
+    ent = pivot_entries(qs, data, piv)
+    for qi in range(3):
+        X, Y, total = gate.collect_log(tab, _t(qs[qi:qi + 1]), ef=24)
+        rec = []
+        search(data, G, qs[qi], int(ent[qi]), 24, 10, mode="finger", tables=orc, record=rec)
+        F = np.concatenate([edge_features(qs[qi], data[c], data[nb], orc["P"], ub2) for c, nb, _, ub2 in rec])
+        d2 = np.concatenate([sqdist(qs[qi], data[nb]) for _, nb, _, _ in rec])
+        X, Y = X.cpu().numpy().astype(np.float64), Y.cpu().numpy().astype(np.float64)
+        assert X.shape == F.shape, (X.shape, F.shape)
+        r = 64
+        # sign-free comparisons: scalars, and w_i u_i per basis row
+        np.testing.assert_allclose(X[:, 2 * r:], F[:, 2 * r:], rtol=2e-4, atol=2e-4)
+        np.testing.assert_allclose(X[:, :r] * X[:, r:2 * r], F[:, :r] * F[:, r:2 * r], atol=2e-4)
+        np.testing.assert_array_equal(Y[:, 0], d2)
+        t = api.finger_gate_targets(_t(X.astype(np.float32)), _t(Y.astype(np.float32)), X.shape[0], r)
+        assert np.all(np.abs(t.cpu().numpy()) <= 1.0 + 1e-3)
+
+
+def test_gated_search_matches_oracle(api):
+    _say("gated search with seeded gate weights vs the oracle's gated search")
+    from workloads import gate_weights
+    data, qs, G, _, piv = helpers.c2_small()
+    tab = api.finger_build_tables(_t(data), _t(G), rank=64, pivots=piv, seed=0)
+    orc = oracle_build(data, G, 64, n_samples=100_000, seed=0)
+    H, eps_gate, ef = 64, 0.02, 32
+    w = gate_weights(2 * 64 + 4, H, seed=5)
+    api.finger_gate_attach(tab, w, 2 * 64 + 4, H, eps_gate)
+    gi, gd, gc = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), mode=2, k=10, ef=ef, entry=-1))
+    ent = pivot_entries(qs, data, piv)
+    w64 = w.astype(np.float64)
+
+    def est(q, cur, nbrs, ub2):
+        return gated_estimate(q, data[cur], data[nbrs], orc, w64, H, eps_gate, ub2)
+
+    sub = np.arange(0, qs.shape[0], 2)
+    oi, od, oc, margin = search_batch(data, G, qs[sub], ent[sub], ef, 10, mode="finger",
+                                      tables=orc, estimator=est)
+    # features are rounded to bf16 on both sides; float32 vs float64 inputs
+    # can land on different sides of a rounding boundary, a relative effect
+    # on the estimate far below 1e-4
+    safe = margin > 1e-4
+    same = (gi[sub] == oi).all(1)
+    _say(f"gated vs oracle: {safe.mean():.2f} of queries with margin > 1e-4, identical on "
+         f"{same[safe].mean() if safe.any() else float('nan'):.3f} of them, {same.mean():.3f} overall; "
+         f"skip rate {gc[:, 3].sum() / max(gc[:, 2].sum(), 1):.3f}")
+    assert same.mean() >= 0.99
+    assert same[safe].all()
+    np.testing.assert_array_equal(gc[sub][safe][:, :6], oc[safe])
+
+
+def test_gate_training_and_gain(api):
+    _say("train the gate on logged searches (GPU kernels), then gated vs FINGER on held-out queries")
+    from paper_2206_11408_amd import gate
+    from workloads import SPECS, make_points
+    data, qs, G, _, piv = helpers.c2_small()
+    tab = api.finger_build_tables(_t(data), _t(G), rank=64, pivots=piv, seed=0)
+    spec = SPECS["c2"].scaled(n=data.shape[0], n_centers=20, nq=2000, seed=0)
+    _, train_q = make_points(spec)
+    train_q = train_q[200:]   # same mixture; the first 200 draws are the test queries
+    info = gate.fit_gate(tab, _t(train_q), ef=48, hidden=64, epochs=3, batch=2048, lr=2e-3,
+                         capacity=1 << 20, log=_say)
+    _say(f"gate: rows {info['rows']}, loss by epoch {info['loss']}, eps_gate {info['eps_gate']:.4f}")
+    assert info["loss"][-1] < info["loss"][0]
+    gt_i, _ = api.finger_exact_knn(_t(data), _t(qs), 10)
+    gt_i = gt_i.cpu().numpy()
+
+    def rec(ids):
+        return float(np.mean([np.isin(ids[i], gt_i[i]).mean() for i in range(ids.shape[0])]))
+
+    for ef in (24, 48):
+        fi, _, fc = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), mode=1, k=10, ef=ef, entry=-1))
+        gi, _, gc = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), mode=2, k=10, ef=ef, entry=-1))
+        _say(f"ef={ef}: FINGER recall {rec(fi):.4f} exact/q {fc[:, 1].mean():.1f} "
+             f"skip {fc[:, 3].sum() / max(fc[:, 2].sum(), 1):.3f} | gated recall {rec(gi):.4f} "
+             f"exact/q {gc[:, 1].mean():.1f} skip {gc[:, 3].sum() / max(gc[:, 2].sum(), 1):.3f}")
+        assert (gc[:, 6] == 0).all()

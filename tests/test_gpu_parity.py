@@ -105,6 +105,8 @@ def test_tables_against_oracle(api):
     np.testing.assert_array_equal(smp, np.stack([c, d, dp], 1))
     P = tab.read(L.T_P_F64)
     np.testing.assert_allclose(P.T @ P, orc["P"].T @ orc["P"], atol=1e-9)
+    # canonical signs make the bases equal row by row
+    np.testing.assert_allclose(P, orc["P"], atol=1e-8)
     ev = tab.read(L.T_EIGVALS)
     np.testing.assert_allclose(np.sqrt(np.maximum(ev[:r], 0)), orc["singular_values"][:r], rtol=1e-9)
     inf = tab.info()

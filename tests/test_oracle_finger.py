@@ -73,6 +73,16 @@ def test_prop31_svd_basis_is_top_eigvecs_and_optimal(c1_small):
         assert obj(Q.T) > best
 
 
+def test_canonical_signs():
+    from oracle.build import canonical_signs
+    rng = np.random.default_rng(8)
+    Q, _ = np.linalg.qr(rng.normal(size=(9, 4)))
+    P = canonical_signs(-Q.T)
+    for row in P:
+        assert row[np.argmax(np.abs(row))] > 0
+    np.testing.assert_allclose(P.T @ P, Q @ Q.T, atol=1e-12)
+
+
 def test_dm_matches_moments_exactly():
     rng = np.random.default_rng(0)
     X = rng.normal(0.3, 0.1, 5000)

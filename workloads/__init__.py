@@ -10,6 +10,7 @@ produces and neither is imported here.
 from .gen import (  # noqa: F401
     WorkloadSpec,
     SPECS,
+    gate_weights,
     make_points,
 )
 from .graph import (  # noqa: F401

@@ -82,6 +82,19 @@ def _draw(rng: np.random.Generator, spec: WorkloadSpec, centers: np.ndarray,
     return out
 
 
+def gate_weights(in_dim: int, hidden: int, seed: int, scale: float = 0.1,
+                 out_bias: float = 0.4) -> np.ndarray:
+    """Seeded weights for a gate network (float32, the C ABI's layout
+    W1, b1, W2, b2, W3, b3): uniform entries of size ``scale`` and an output
+    bias near a typical residual cosine, so a gated search screens sensibly.
+    Used where both the library and the oracle need the same network."""
+    rng = np.random.default_rng(seed)
+    n = hidden * in_dim + hidden * hidden + 3 * hidden + 1
+    w = rng.uniform(-scale, scale, n)
+    w[-1] = out_bias
+    return w.astype(np.float32)
+
+
 def make_points(spec: WorkloadSpec) -> tuple[np.ndarray, np.ndarray]:
     """Return (data [n, m], queries [nq, m]) as C-contiguous float32."""
     rng = np.random.default_rng(spec.seed)
