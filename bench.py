@@ -95,6 +95,9 @@ def main() -> int:
                          "with the adjacency row)")
     ap.add_argument("--ef-plain", type=int, default=0, help="skip the plain sweep, use this ef")
     ap.add_argument("--ef-finger", type=int, default=0, help="skip the FINGER sweep, use this ef")
+    ap.add_argument("--gate", type=int, default=0,
+                    help="train the learned gate on this many extra queries (0 = skip) and "
+                         "report the gated search")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (the reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -199,19 +202,29 @@ def main() -> int:
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
         for _ in range(warmup):
             run(tab, mode, ef, out, prefetch=prefetch)
+        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(steps)]
+        for e0, e1 in pairs:   # create the HIP events before the timed region
+            e0.record()
+            e1.record()
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1, code_prefetch=prefetch)
         torch.cuda.synchronize()
-        kms = []
         t0 = time.perf_counter()
-        for _ in range(steps):
-            run(tab, mode, ef, out, time_kernel=True, prefetch=prefetch)
-            kev[1].synchronize()
-            kms.append(kev[0].elapsed_time(kev[1]))
+        ev[0].record()
+        for e0, e1 in pairs:
+            p.kernel_events[0] = e0.cuda_event
+            p.kernel_events[1] = e1.cuda_event
+            api.finger_search(tab, d_q, p, out=out)
+        ev[1].record()
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
+        gpu_total = ev[0].elapsed_time(ev[1]) * 1e-3
+        kms = [e0.elapsed_time(e1) for e0, e1 in pairs]
         ids, dist, ctr = (x.cpu().numpy() for x in out)
         B = algorithmic_bytes(ctr, spec.m, spec.max_degree, a.rank if mode else 0, code_bytes, 10, fp8)
         kavg = float(np.mean(kms))
         return dict(ef=ef, qps=nq * steps / total, ms_per_step=total / steps * 1e3,
+                    gpu_ms_per_step=gpu_total / steps * 1e3,
                     kernel_ms=kavg, kernel_ms_min=float(np.min(kms)), alg_bytes=B,
                     alg_gbs=B / (kavg * 1e-3) / 1e9, recall=recall(ids, dist),
                     exact=float(ctr[:, 1].mean()), skipped=float(ctr[:, 3].mean()),
@@ -257,6 +270,26 @@ def main() -> int:
                               kernel_ms=round(tx["kernel_ms"], 4), alg_gbs=round(tx["alg_gbs"], 1),
                               speedup_vs_plain=round(tx["qps"] / tp["qps"], 4))
         log(f"finger {variant} timed: {tx}")
+
+    gated = None
+    if a.gate > 0:
+        from paper_2206_11408_amd import gate as gate_mod
+        tr_spec = SPECS["c2"].scaled(n=a.n, n_centers=a.clusters, nq=a.nq + a.gate)
+        _, tr_q = make_points(tr_spec)   # same mixture; rows after the first nq are new draws
+        t0 = time.time()
+        info = gate_mod.fit_gate(tabF, torch.as_tensor(tr_q[a.nq:], device=dev), ef=op_f["ef"],
+                                 hidden=64, epochs=2, batch=4096, lr=2e-3, capacity=1 << 24,
+                                 log=log)
+        torch.cuda.synchronize()
+        log(f"gate trained in {time.time() - t0:.1f}s on {info['rows']} rows "
+            f"(screened {info['screened']}), loss {info['loss']}, eps_gate {info['eps_gate']:.4f}")
+        sw_g, op_g = sweep(tabF, L.MODE_GATED)
+        tg = timed(tabF, L.MODE_GATED, op_g["ef"], a.steps, a.warmup, cb, fp8)
+        log(f"gated  timed: {tg}")
+        gated = dict(ef=op_g["ef"], recall=round(tg["recall"], 4), qps=round(tg["qps"], 1),
+                     kernel_ms=round(tg["kernel_ms"], 4), speedup_vs_plain=round(tg["qps"] / tp["qps"], 4),
+                     speedup_vs_finger=round(tg["qps"] / tf["qps"], 4), exact=round(tg["exact"], 1),
+                     train_rows=info["rows"], eps_gate=round(info["eps_gate"], 5))
 
     # ------------------------------------------------------ CPU baseline
     cpu = None
@@ -309,6 +342,8 @@ def main() -> int:
     }
     if extra:
         line["extra_codes"] = extra
+    if gated:
+        line["gated"] = gated
     print(json.dumps(line), flush=True)
     return 0
 

@@ -421,7 +421,7 @@ namespace {
 
 struct Plan {
   int ef_max, vis_cap, waves, lds, spill_slots;
-  size_t off_qq, off_pq, off_ent, off_queue, off_qscr, off_spill, total;
+  size_t off_qq, off_pq, off_ent, off_queue, off_qscr, off_spill, off_qn, total;
 };
 
 int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan* pl) {
@@ -457,8 +457,10 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
     return fail(FINGER_EINVAL, "visited_capacity = %d must be a power of two >= 256", vis_cap);
   const int gate_h = p->mode == FINGER_MODE_GATED ? t->gate_h : 0;
   const int gate_in = p->mode == FINGER_MODE_GATED ? t->gate_in : 0;
-  const int lds_wave = search_lds_bytes(ef_max, vis_cap, t->r, 0, gate_in);
-  const int lds_shared = search_lds_bytes(0, 0, t->r, gate_h, gate_in) - search_lds_bytes(0, 0, t->r, 0, 0);
+  const int r_used = p->mode == FINGER_MODE_PLAIN ? 0 : t->r;
+  const int lds_wave = search_lds_bytes(ef_max, vis_cap, r_used, t->m, 0, gate_in);
+  const int lds_shared = search_lds_bytes(0, 0, r_used, t->m, gate_h, gate_in) -
+                         search_lds_bytes(0, 0, r_used, t->m, 0, gate_in);
   const int lds_limit = 160 * 1024;
   const int wpb = p->mode == FINGER_MODE_GATED ? 4 : 1;
   if (lds_shared + wpb * lds_wave > lds_limit)
@@ -481,6 +483,9 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   const int spill_slots = std::min(16384, std::max(1024, next_pow2(8 * ef_max)));
   pl->off_spill = off; off += align256((size_t)waves * spill_slots * 4);
   pl->spill_slots = spill_slots;
+  // angular metric: the search reads unit-normalized copies of the queries
+  pl->off_qn = off;
+  if (t->metric == FINGER_ANGULAR) off += align256((size_t)nq * t->m * 4);
   pl->total = off;
   pl->ef_max = ef_max;
   pl->vis_cap = vis_cap;
@@ -529,10 +534,17 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   int32_t* queue = reinterpret_cast<int32_t*>(ws + pl.off_queue);
   float* qscr = reinterpret_cast<float*>(ws + pl.off_qscr);
   int32_t* spill = reinterpret_cast<int32_t*>(ws + pl.off_spill);
+  if (t->metric == FINGER_ANGULAR) {
+    float* qn = reinterpret_cast<float*>(ws + pl.off_qn);
+    HIPCHK(launch_normalize_rows(queries, nq, t->m, qn, s));
+    queries = qn;
+  }
   HIPCHK(hipMemsetAsync(queue, 0, 4, s));
   HIPCHK(hipMemsetAsync(spill, 0xFF, (size_t)pl.waves * pl.spill_slots * 4, s));
   const bool need_prep = p->mode != FINGER_MODE_PLAIN || p->entry == -1;
-  if (need_prep) HIPCHK(launch_query_prep(*t, queries, nq, qq, pq, p->entry == -1 ? ent : nullptr, qscr, s));
+  if (need_prep)
+    HIPCHK(launch_query_prep(*t, queries, nq, qq, pq, p->entry == -1 ? ent : nullptr, qscr, s,
+                             p->mode != FINGER_MODE_PLAIN));
   SearchLaunch L{};
   L.queries = queries;
   L.nq = nq;
@@ -590,6 +602,12 @@ int finger_estimate_edges(const finger_tables* th, const float* queries, int64_t
   tq.npiv = 0;  // Pq and |q|^2 only
   float* qq = buf.p;
   float* pq = buf.p + (nq + 63) / 64 * 64;
+  DevBuf<float> qn;
+  if (t->metric == FINGER_ANGULAR) {
+    if ((st = dev_alloc(reinterpret_cast<void**>(&qn.p), (size_t)nq * t->m * 4, "normalized queries")) != FINGER_OK) return st;
+    HIPCHK(launch_normalize_rows(queries, nq, t->m, qn.p, s));
+    queries = qn.p;
+  }
   HIPCHK(launch_query_prep(tq, queries, nq, qq, pq, nullptr, nullptr, s));
   HIPCHK(launch_estimate_edges(*t, queries, qq, pq, q_index, centers, slots, n_items, out_est, out_t_hat, s));
   HIPCHK(hipStreamSynchronize(s));

@@ -161,8 +161,116 @@ __global__ void __launch_bounds__(256) k_qprep(const float* Q, int64_t nq, const
   }
 }
 
+// Pivot scores |x|^2 - 2 q.x on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..+8) and
+// B[8(l/16)..+8)[l%16]; D[4(l/16)+v][l%16]).  Queries and pivots are rounded
+// to bf16 (exact for integers up to 256), products accumulate in float32.
+// The scores only rank candidates: the final choice is re-ranked with exact
+// float32 distances in k_qfinish.  Per 64-column tile, each query keeps its
+// two best (score, column).
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+constexpr int PK = 32, PLD = 40;  // K slab and padded LDS row (bf16 elements)
+
+__global__ void __launch_bounds__(256) k_pivot_scores(const float* Q, int64_t nq, const float* B,
+                                                      const float* Bnorm, int pcols, int pend,
+                                                      int K, float2* best, int ntiles) {
+  __shared__ __align__(16) __bf16 As[BM * PLD], Bs[BN * PLD];
+  __shared__ float Ct[BM * 65];
+  const int64_t r0 = (int64_t)blockIdx.y * BM;
+  const int tile = blockIdx.x;
+  const int64_t c0 = pcols + (int64_t)tile * BN;
+  const int w = threadIdx.x / 64, l = threadIdx.x & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  f4v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += PK) {
+    __syncthreads();
+    // stage: 64 rows x 32 k of each operand, 8 elements per thread
+    {
+      const int row = threadIdx.x >> 2, kc = (threadIdx.x & 3) * 8;
+      float va[8], vb[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) { va[e] = 0.f; vb[e] = 0.f; }
+      if (k0 + kc < K) {  // K % 4 == 0 and slabs of 8 never straddle K when K % 8 == 0
+        const int64_t qa = r0 + row, cb = c0 + row;
+#pragma unroll
+        for (int e = 0; e < 8; e += 4) {
+          if (k0 + kc + e < K) {
+            if (qa < nq) {
+              const float4 v = *reinterpret_cast<const float4*>(Q + qa * K + k0 + kc + e);
+              va[e] = v.x; va[e + 1] = v.y; va[e + 2] = v.z; va[e + 3] = v.w;
+            }
+            if (cb < pend) {
+              const float4 v = *reinterpret_cast<const float4*>(B + cb * K + k0 + kc + e);
+              vb[e] = v.x; vb[e + 1] = v.y; vb[e + 2] = v.z; vb[e + 3] = v.w;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        As[row * PLD + kc + e] = (__bf16)va[e];
+        Bs[row * PLD + kc + e] = (__bf16)vb[e];
+      }
+    }
+    __syncthreads();
+    b8v a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const b8v*>(&As[(wr + 16 * i + (l & 15)) * PLD + 8 * (l >> 4)]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      b[j] = *reinterpret_cast<const b8v*>(&Bs[(wc + 16 * j + (l & 15)) * PLD + 8 * (l >> 4)]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = wr + 16 * i + 4 * (l >> 4) + v;
+        const int cl = wc + 16 * j + (l & 15);
+        const int64_t col = c0 + cl;
+        Ct[rr * 65 + cl] = col < pend ? Bnorm[col] - 2.f * acc[i][j][v] : __int_as_float(0x7f800000);
+      }
+  __syncthreads();
+  for (int rr = w; rr < BM; rr += 4) {
+    const int64_t row = r0 + rr;
+    const float s = Ct[rr * 65 + l];
+    const int col = (int)c0 + l;
+    float s1 = s;
+    int c1 = col;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const float so = __shfl_xor(s1, o, 64);
+      const int co = __shfl_xor(c1, o, 64);
+      if (so < s1 || (so == s1 && co < c1)) { s1 = so; c1 = co; }
+    }
+    float s2 = (col == c1) ? __int_as_float(0x7f800000) : s;
+    int c2 = col;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const float so = __shfl_xor(s2, o, 64);
+      const int co = __shfl_xor(c2, o, 64);
+      if (so < s2 || (so == s2 && co < c2)) { s2 = so; c2 = co; }
+    }
+    if (l == 0 && row < nq) {
+      best[(row * ntiles + tile) * 2] = make_float2(s1, __int_as_float(c1));
+      best[(row * ntiles + tile) * 2 + 1] = make_float2(s2, __int_as_float(c2));
+    }
+  }
+}
+
 // Per query (one wave): norms, then among the per-tile best pivot scores
-// the 4 lowest are re-ranked by exact direct differences; the nearest
+// the 8 lowest are re-ranked by exact direct differences; the nearest
 // pivot (ties to the smaller pivot index) becomes the entry.
 __global__ void k_qfinish(const float* Q, int64_t nq, int m, const float* B, int pcols,
                           const int32_t* piv_ids, int npiv, const float2* best, int ntiles,
@@ -195,7 +303,7 @@ __global__ void k_qfinish(const float* Q, int64_t nq, int m, const float* B, int
   }
   float bestd = __int_as_float(0x7f800000);
   int bestc = 0x7fffffff;
-  for (int round = 0; round < 4; ++round) {
+  for (int round = 0; round < 8; ++round) {
     // wave-wide minimum of the lanes' heads
     float s1 = cs[0];
     int c1 = cc[0];
@@ -237,17 +345,24 @@ size_t query_prep_scratch_bytes(const Tables& t, int64_t nq) {
 }
 
 hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float* qq, float* Pq,
-                             int32_t* entries, float* scratch, hipStream_t s) {
+                             int32_t* entries, float* scratch, hipStream_t s, bool need_pq) {
   if (nq == 0) return hipSuccess;
   const int rpad = rpad_of(t.r);
   const int rcols = (rpad + BN - 1) / BN * BN;  // P block padded to whole tiles
   const int ntiles = t.npiv > 0 ? (t.npiv + BN - 1) / BN : 0;
   float2* best = reinterpret_cast<float2*>(scratch);
-  if (t.qprep_cols > 0 && (t.r > 0 || ntiles > 0)) {
-    dim3 grid((unsigned)(t.qprep_cols / BN), (unsigned)((nq + BM - 1) / BM));
-    // Pq has row stride rpad; pivot columns start at rcols
-    hipLaunchKernelGGL(k_qprep, grid, dim3(256), 0, s, Q, nq, t.qprep_B, t.qprep_Bnorm,
-                       t.qprep_cols, t.m, rpad, rcols, rcols + t.npiv, Pq, best, ntiles);
+  if (t.r > 0 && need_pq) {
+    // Pq = P q in float32 MFMA (the estimate needs full precision)
+    dim3 grid((unsigned)(rcols / BN), (unsigned)((nq + BM - 1) / BM));
+    hipLaunchKernelGGL(k_qprep, grid, dim3(256), 0, s, Q, nq, t.qprep_B, t.qprep_Bnorm, rcols, t.m,
+                       rpad, rcols, rcols, Pq, best, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (ntiles > 0) {
+    dim3 grid((unsigned)ntiles, (unsigned)((nq + BM - 1) / BM));
+    hipLaunchKernelGGL(k_pivot_scores, grid, dim3(256), 0, s, Q, nq, t.qprep_B, t.qprep_Bnorm,
+                       rcols, rcols + t.npiv, t.m, best, ntiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

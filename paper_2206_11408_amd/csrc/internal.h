@@ -75,7 +75,7 @@ hipError_t launch_gemm_nt(const float* A, int64_t rows, const float* B, int64_t 
 // query preparation: qq[i] = |q_i|^2, Pq[i][0..r) = P q_i, and (if npiv > 0)
 // entries[i] = nearest pivot id by exact squared distance
 hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float* qq, float* Pq,
-                             int32_t* entries, float* scratch, hipStream_t s);
+                             int32_t* entries, float* scratch, hipStream_t s, bool need_pq = true);
 size_t query_prep_scratch_bytes(const Tables& t, int64_t nq);
 
 struct SearchLaunch {
@@ -105,7 +105,7 @@ struct SearchLaunch {
 };
 hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s);
 bool search_prefetch_supported(const Tables& t);
-int search_lds_bytes(int ef_max, int vis_cap, int r, int gate_h, int gate_in);
+int search_lds_bytes(int ef_max, int vis_cap, int r, int m, int gate_h, int gate_in);
 
 hipError_t launch_estimate_edges(const Tables& t, const float* Q, const float* qq,
                                  const float* Pq, const int32_t* qi, const int32_t* ci,

@@ -246,8 +246,10 @@ __device__ __forceinline__ void load_query(const KArgs& a, int64_t qi, float4* q
 // exact squared distances of the `cnt` ids in ids_lds[0..cnt) to the query;
 // results go to d_lds[0..cnt).  G lanes share one vector; NP passes of
 // 64/G vectors are in flight together.
+// qv: the query chunks this lane needs, either in registers or (qlds) read
+// from the wave's LDS copy of the query when needed
 template <int G, int T4, int NP>
-__device__ __forceinline__ void exact_dists(const KArgs& a, const float4* qv,
+__device__ __forceinline__ void exact_dists(const KArgs& a, const float4* qv, const float4* qlds,
                                             const int* __restrict__ ids_lds, int cnt,
                                             float* __restrict__ d_lds) {
   constexpr int NPP = 64 / G;
@@ -278,8 +280,10 @@ __device__ __forceinline__ void exact_dists(const KArgs& a, const float4* qv,
       float acc = 0.f;
 #pragma unroll
       for (int t = 0; t < T4; ++t) {
-        const float dx = qv[t].x - xv[h][t].x, dy = qv[t].y - xv[h][t].y;
-        const float dz = qv[t].z - xv[h][t].z, dw = qv[t].w - xv[h][t].w;
+        const int j = lg + G * t;
+        const float4 q = qlds != nullptr ? (j < a.m4 ? qlds[j] : make_float4(0.f, 0.f, 0.f, 0.f)) : qv[t];
+        const float dx = q.x - xv[h][t].x, dy = q.y - xv[h][t].y;
+        const float dz = q.z - xv[h][t].z, dw = q.w - xv[h][t].w;
         acc += dx * dx + dy * dy + dz * dz + dw * dw;
       }
       acc = group_sum<G>(acc);
@@ -320,7 +324,7 @@ __device__ __forceinline__ float gate_edge(const KArgs& a, const uint16_t* __res
 }
 
 template <int MODE, int CODE, int G, int T4, bool PREFETCH>
-__global__ void __launch_bounds__(256) k_search(KArgs a) {
+__device__ __forceinline__ void search_body(const KArgs& a) {
   extern __shared__ __align__(16) char smem[];
   const int l = lane_id();
   const int wib = threadIdx.x / 64;
@@ -337,7 +341,12 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
   float* cd = reinterpret_cast<float*>(cid + 64);
   int* cflag = reinterpret_cast<int*>(cd + 64);
   float* wv = reinterpret_cast<float*>(cflag + 64);  // [rpad] (screening)
-  float* feat = wv + a.rpad;                         // gated: [spp][r + 4], then [64] hidden
+  float* pqv = wv + a.rpad;                          // [rpad] this query's Pq
+  float4* qsh = reinterpret_cast<float4*>(pqv + a.rpad);  // [m] the query (screening modes)
+  float* feat = reinterpret_cast<float*>(qsh) + (MODE != FINGER_MODE_PLAIN ? a.m : 0);
+  // gated: feat = [spp][r + 4], then [64] hidden
+  // screening modes keep the query in LDS (registers go to the screen)
+  const float4* qlds = (MODE != FINGER_MODE_PLAIN) ? qsh : nullptr;
 
   const uint16_t* gw = nullptr;
   const float* gb = nullptr;
@@ -383,15 +392,17 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
       status |= 2;
     }
 
-    float4 qv[T4];
-    load_query<G, T4>(a, qi, qv);
+    float4 qv[MODE == FINGER_MODE_PLAIN ? T4 : 1];
+    if constexpr (MODE == FINGER_MODE_PLAIN) {
+      load_query<G, T4>(a, qi, qv);
+    } else {
+      const float4* q4 = reinterpret_cast<const float4*>(a.queries + qi * a.m);
+      for (int j = l; j < a.m4; j += 64) qsh[j] = q4[j];
+    }
     float qq = 0.f;
-    float pq_l[4] = {0.f, 0.f, 0.f, 0.f};  // Pq elements l, l+64, l+128, l+192
     if constexpr (MODE != FINGER_MODE_PLAIN) {
       qq = a.qq[qi];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (l + 64 * i < a.rpad) pq_l[i] = a.pq[qi * a.rpad + l + 64 * i];
+      for (int i = l; i < a.rpad; i += 64) pqv[i] = a.pq[qi * a.rpad + i];
     }
 
     for (int i = l; i < a.vis_cap; i += 64) vis[i] = -1;
@@ -404,7 +415,7 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
       cid[0] = entry;
     }
     wave_lds_sync();
-    exact_dists<G, T4, 1>(a, qv, cid, 1, cd);
+    exact_dists<G, T4, 1>(a, qv, qlds, cid, 1, cd);
     int cur_buf = 0;
     if (l == 0) {
       tD[0][0] = cd[0];
@@ -413,81 +424,45 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
     wave_lds_sync();
     int tn = 1;
     int n_exp = 0, n_exact = 1, n_scr = 0, n_skip = 0, n_vis = 1, n_prep = 0;
-    // rows of the runner-up unexpanded entry, requested one expansion early
-    // (used only if that entry is the next one expanded)
-    int pf_id = -1, pf_nb = -1;
-    float pf_al = 0.f, pf_rh = 0.f, pf_cc = 0.f, pf_pc = 0.f;
 
     while (true) {
       float* TD = tD[cur_buf];
       int* TI = tI[cur_buf];
-      // 1. the best unexpanded entry of T (and the runner-up)
-      int j = -1, j2 = -1;
-      for (int b0 = 0; b0 < tn && j2 < 0; b0 += 64) {
+      // 1. the best unexpanded entry of T
+      int j = -1;
+      for (int b0 = 0; b0 < tn; b0 += 64) {
         const int i = b0 + l;
         const bool un = i < tn && ((uint32_t)TI[i] & kExpanded) == 0u;
-        uint64_t bm = ballot(un);
-        if (bm && j < 0) {
+        const uint64_t bm = ballot(un);
+        if (bm) {
           j = b0 + __ffsll((unsigned long long)bm) - 1;
-          bm &= bm - 1ull;
+          break;
         }
-        if (bm) j2 = b0 + __ffsll((unsigned long long)bm) - 1;
       }
       if (j < 0) break;
       const int cur = TI[j];
       const float dcur = TD[j];
       const float ub2 = TD[tn - 1];
-      const int nxt = j2 >= 0 ? TI[j2] : -1;
       wave_lds_sync();
       if (l == 0) TI[j] = (int)((uint32_t)cur | kExpanded);
       ++n_exp;
 
       const bool screening = (MODE != FINGER_MODE_PLAIN) && n_exp > a.warmup && tn == ef_eff;
-      // 2. one round trip: adjacency (+ screening inputs), unless they were
-      // requested during the previous expansion
-      const bool hit = cur == pf_id;
-      int nb = pf_nb;
-      if (!hit && l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
-      float al = 0.f, rh = 0.f, ccv = 0.f;
-      float pcv[4] = {0.f, 0.f, 0.f, 0.f};
+      // 2. one round trip: adjacency (+ screening inputs)
+      int nb = -1;
+      if (l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
+      float al = 0.f, rh = 0.f, ccv = 0.f, pc0 = 0.f;
       Chunk<CODE> code;
       if constexpr (MODE != FINGER_MODE_PLAIN) {
         if (screening) {
-          if (hit && a.rpad <= 64) {
-            al = pf_al;
-            rh = pf_rh;
-            ccv = pf_cc;
-            pcv[0] = pf_pc;
-          } else {
-            if (csub < a.deg) {
-              al = a.alpha[(int64_t)cur * a.deg + csub];
-              rh = a.rho[(int64_t)cur * a.deg + csub];
-            }
-            ccv = a.cc[cur];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (l + 64 * i < a.rpad) pcv[i] = a.pc[(int64_t)cur * a.rpad + l + 64 * i];
-          }
-          if constexpr (PREFETCH)
-            if (csub < a.deg)
+          if (csub < a.deg) {
+            al = a.alpha[(int64_t)cur * a.deg + csub];
+            rh = a.rho[(int64_t)cur * a.deg + csub];
+            if constexpr (PREFETCH)
               code.load(a.codes, ((int64_t)cur * a.deg + csub) * a.rpad + ch * kChunk);
-        }
-      }
-      // request the runner-up's rows now; they arrive while this expansion runs
-      pf_id = nxt;
-      pf_nb = -1;
-      if (nxt >= 0) {
-        if (l < a.deg) pf_nb = a.graph[(int64_t)nxt * a.deg + l];
-        if constexpr (MODE != FINGER_MODE_PLAIN) {
-          // the runner-up is screened only if T is full by then
-          if (n_exp + 1 > a.warmup && a.rpad <= 64) {
-            if (csub < a.deg) {
-              pf_al = a.alpha[(int64_t)nxt * a.deg + csub];
-              pf_rh = a.rho[(int64_t)nxt * a.deg + csub];
-            }
-            pf_cc = a.cc[nxt];
-            if (l < a.rpad) pf_pc = a.pc[(int64_t)nxt * a.rpad + l];
           }
+          ccv = a.cc[cur];
+          if (l < a.rpad) pc0 = a.pc[(int64_t)cur * a.rpad + l];
         }
       }
       // 3. visited test-and-set
@@ -513,13 +488,11 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
           const float rq2 = fmaxf(qq - aq * qc, 0.f);
           const float rq = sqrtf(rq2);
           float w2 = 0.f;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (l + 64 * i < a.rpad) {
-              const float w = pq_l[i] - aq * pcv[i];
-              wv[l + 64 * i] = w;
-              w2 += w * w;
-            }
+          for (int i = l; i < a.rpad; i += 64) {
+            const float pc = i < 64 ? pc0 : a.pc[(int64_t)cur * a.rpad + i];
+            const float w = pqv[i] - aq * pc;
+            wv[i] = w;
+            w2 += w * w;
           }
           w2 = wave_sum(w2);
           const float inv_w = w2 > 0.f ? 1.0f / sqrtf(w2) : 0.f;
@@ -640,7 +613,7 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
       // 5. exact distances of the survivors
       // plain search keeps two passes of vectors in flight; after screening
       // few neighbours survive and one pass is enough
-      exact_dists<G, T4, MODE == FINGER_MODE_PLAIN ? 2 : 1>(a, qv, cid, S2, cd);
+      exact_dists<G, T4, MODE == FINGER_MODE_PLAIN ? 2 : 1>(a, qv, qlds, cid, S2, cd);
 
       // 6. admission: lanes 0..S2-1 hold (cd, cid)
       uint64_t key = ~0ull;
@@ -741,8 +714,22 @@ __global__ void __launch_bounds__(256) k_search(KArgs a) {
 }
 
 template <int MODE, int CODE, int G, int T4, bool PF>
+__global__ void __launch_bounds__(256) k_search(KArgs a) {
+  search_body<MODE, CODE, G, T4, PF>(a);
+}
+
+// FINGER screening: hold the register budget of four waves per SIMD (the
+// search is latency bound, so resident waves matter more than a few spills)
+template <int MODE, int CODE, int G, int T4, bool PF>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_search_w4(KArgs a) {
+  search_body<MODE, CODE, G, T4, PF>(a);
+}
+
+template <int MODE, int CODE, int G, int T4, bool PF>
 hipError_t launch_k(const KArgs& a, int blocks, int lds, hipStream_t s) {
-  auto fn = k_search<MODE, CODE, G, T4, PF>;
+  auto fn = MODE == FINGER_MODE_FINGER ? k_search_w4<MODE, CODE, G, T4, PF>
+                                       : k_search<MODE, CODE, G, T4, PF>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
@@ -775,9 +762,9 @@ int gate_shared_bytes(int gate_h, int gate_in) {
   return ((2 * nw + 15) & ~15) + ((4 * (2 * gate_h + 1) + 15) & ~15);
 }
 
-int wave_bytes(int ef_max, int vis_cap, int r, int gate_in) {
+int wave_bytes(int ef_max, int vis_cap, int r, int m, int gate_in) {
   const int rpad = rpad_of(r);
-  int b = 16 * ef_max + 4 * vis_cap + 64 * 8 + 64 * 4 * 3 + 4 * rpad;
+  int b = 16 * ef_max + 4 * vis_cap + 64 * 8 + 64 * 4 * 3 + 8 * rpad + (r > 0 ? 4 * m : 0);
   if (gate_in > 0) {
     const int spp = 64 / (rpad / 16);  // at most this many slots per pass
     b += 4 * (spp * (r + 4) + 64);
@@ -810,8 +797,8 @@ void fill_common(KArgs& a, const Tables& t) {
 
 }  // namespace
 
-int search_lds_bytes(int ef_max, int vis_cap, int r, int gate_h, int gate_in) {
-  return gate_shared_bytes(gate_h, gate_in) + wave_bytes(ef_max, vis_cap, r, gate_in);
+int search_lds_bytes(int ef_max, int vis_cap, int r, int m, int gate_h, int gate_in) {
+  return gate_shared_bytes(gate_h, gate_in) + wave_bytes(ef_max, vis_cap, r, m, gate_in);
 }
 
 bool search_prefetch_supported(const Tables& t) {
@@ -858,7 +845,8 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   // grained; the gated mode shares its weights among 4 waves
   a.waves_per_block = gated ? 4 : 1;
   a.lds_shared_bytes = gated ? gate_shared_bytes(a.gate_h, a.gate_in) : 0;
-  a.lds_wave_bytes = wave_bytes(L.ef_max, L.vis_cap, t.r, gated ? a.gate_in : 0);
+  a.lds_wave_bytes = wave_bytes(L.ef_max, L.vis_cap, L.mode == FINGER_MODE_PLAIN ? 0 : t.r, t.m,
+                                gated ? a.gate_in : 0);
   const int lds = a.lds_shared_bytes + a.waves_per_block * a.lds_wave_bytes;
   const int blocks = (L.waves + a.waves_per_block - 1) / a.waves_per_block;
   const bool pf = L.prefetch && search_prefetch_supported(t);

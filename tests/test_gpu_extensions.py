@@ -280,3 +280,39 @@ def test_gate_training_and_gain(api):
              f"skip {fc[:, 3].sum() / max(fc[:, 2].sum(), 1):.3f} | gated recall {rec(gi):.4f} "
              f"exact/q {gc[:, 1].mean():.1f} skip {gc[:, 3].sum() / max(gc[:, 2].sum(), 1):.3f}")
         assert (gc[:, 6] == 0).all()
+
+
+# ---------------------------------------------------------------- angular
+
+def test_angular_metric_normalizes_both_sides(api):
+    _say("angular metric (heavy-tailed 100-d) vs L2 on normalized inputs and the oracle")
+    from paper_2206_11408_amd import _lib as L
+    from oracle.knn import normalize_rows
+    from workloads import SPECS, build_graph, make_points, pick_pivots
+    spec = SPECS["c3b"].scaled(n=20_000, n_centers=20, nq=200)
+    data, qs = make_points(spec)
+    rng = np.random.default_rng(3)
+    raw = (data * rng.uniform(0.5, 4.0, (data.shape[0], 1))).astype(np.float32)
+    rq = (qs * rng.uniform(0.5, 4.0, (qs.shape[0], 1))).astype(np.float32)
+    nd = normalize_rows(raw).astype(np.float32)
+    nq = normalize_rows(rq).astype(np.float32)
+    G, _, _ = build_graph(nd, knn_k=16, max_degree=32)
+    piv = pick_pivots(nd.shape[0], 80, 0)
+    ta = api.finger_build_tables(_t(raw), _t(G), rank=64, metric=L.ANGULAR, pivots=piv,
+                                 code_type=L.CODE_BF16)
+    tl = api.finger_build_tables(_t(nd), _t(G), rank=64, metric=L.L2, pivots=piv,
+                                 code_type=L.CODE_BF16)
+    for mode in (0, 1):
+        a = [x.cpu().numpy() for x in api.finger_search(ta, _t(rq), mode=mode, k=10, ef=48, entry=-1)]
+        b = [x.cpu().numpy() for x in api.finger_search(tl, _t(nq), mode=mode, k=10, ef=48, entry=-1)]
+        same = (a[0] == b[0]).all(1)
+        assert same.mean() >= 0.99
+        np.testing.assert_allclose(a[1][same], b[1][same], rtol=1e-5, atol=1e-6)
+    ent = pivot_entries(nq.astype(np.float64), nd, piv)
+    oi, od, _, _ = search_batch(nd, G, nq, ent, 48, 10)
+    ids = api.finger_search(ta, _t(rq), mode=0, k=10, ef=48, entry=-1)[0].cpu().numpy()
+    assert (ids == oi).all(1).mean() >= 0.99
+    gi, gd = api.finger_exact_knn(_t(raw), _t(rq), 10, metric=L.ANGULAR)
+    from oracle.knn import brute_force_knn
+    bi, bd = brute_force_knn(nd, nq, 10)
+    assert (gi.cpu().numpy() == bi).all(1).mean() >= 0.99
