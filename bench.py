@@ -31,7 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-EF_SWEEP = (10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 200)
+EF_SWEEP = (10, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 52, 56, 60, 64, 72, 80, 96, 112, 128, 160, 200)
 TARGET_RECALL = 0.95
 
 
@@ -98,6 +98,8 @@ def main() -> int:
     ap.add_argument("--gate", type=int, default=0,
                     help="train the learned gate on this many extra queries (0 = skip) and "
                          "report the gated search")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="time the default launch geometry instead of the autotuned one")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (the reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -110,7 +112,7 @@ def main() -> int:
 
     import torch
     from paper_2206_11408_amd import _lib as L
-    from paper_2206_11408_amd import api
+    from paper_2206_11408_amd import api, tune
     from workloads import SPECS, build_graph, make_points, pick_pivots
 
     if not torch.cuda.is_available():
@@ -164,6 +166,8 @@ def main() -> int:
         e.record()
     torch.cuda.synchronize()
 
+    launch = {}   # (mode, code) -> tuned launch settings
+
     def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0):
         p = api.search_params(mode=mode, k=10, ef=ef, entry=-1, code_prefetch=prefetch)
         if time_kernel:
@@ -200,14 +204,29 @@ def main() -> int:
         out = (torch.empty((nq, 10), dtype=torch.int32, device=dev),
                torch.empty((nq, 10), dtype=torch.float32, device=dev),
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
+        if a.tune:
+            base = dict(mode=mode, k=10, ef=ef, entry=-1)
+            ch = tune.autotune(tab, d_q, base, repeats=3, cache_path=None)
+            if prefetch != 0:   # an explicitly requested code-prefetch setting stays fixed
+                best = min((t, c) for t, c in ch["all"] if c["code_prefetch"] == prefetch)[1]
+                ch = dict(best)
+            launch[(mode, id(tab), prefetch)] = {k: ch[k] for k in
+                                                 ("waves_per_cu", "persistent", "code_prefetch",
+                                                  "visited_capacity")}
+            log(f"tuned launch mode={mode}: {launch[(mode, id(tab), prefetch)]}")
+        geo = launch.get((mode, id(tab), prefetch), {})
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1,
+                              code_prefetch=geo.get("code_prefetch", prefetch),
+                              waves_per_cu=geo.get("waves_per_cu", 0),
+                              persistent=geo.get("persistent", 0),
+                              visited_capacity=geo.get("visited_capacity", 0))
         for _ in range(warmup):
-            run(tab, mode, ef, out, prefetch=prefetch)
+            api.finger_search(tab, d_q, p, out=out)
         pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                  for _ in range(steps)]
         for e0, e1 in pairs:   # create the HIP events before the timed region
             e0.record()
             e1.record()
-        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1, code_prefetch=prefetch)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev[0].record()
@@ -223,7 +242,7 @@ def main() -> int:
         ids, dist, ctr = (x.cpu().numpy() for x in out)
         B = algorithmic_bytes(ctr, spec.m, spec.max_degree, a.rank if mode else 0, code_bytes, 10, fp8)
         kavg = float(np.mean(kms))
-        return dict(ef=ef, qps=nq * steps / total, ms_per_step=total / steps * 1e3,
+        return dict(ef=ef, launch=geo, qps=nq * steps / total, ms_per_step=total / steps * 1e3,
                     gpu_ms_per_step=gpu_total / steps * 1e3,
                     kernel_ms=kavg, kernel_ms_min=float(np.min(kms)), alg_bytes=B,
                     alg_gbs=B / (kavg * 1e-3) / 1e9, recall=recall(ids, dist),
@@ -263,11 +282,15 @@ def main() -> int:
         code, _, pfs = variant.partition(":")
         pf = {"pf": 1, "nopf": -1, "": 0}[pfs]
         tab = get_tables(code)
-        sw, op = sweep(tab, L.MODE_FINGER, prefetch=pf)
+        if a.ef_finger:   # a fixed FINGER operating point applies to every code variant
+            op = {"ef": a.ef_finger}
+        else:
+            sw, op = sweep(tab, L.MODE_FINGER, prefetch=pf)
         tx = timed(tab, L.MODE_FINGER, op["ef"], a.steps, a.warmup, code_of[code][1], code == "fp8",
                    prefetch=pf)
         extra[variant] = dict(ef=op["ef"], recall=round(tx["recall"], 4), qps=round(tx["qps"], 1),
                               kernel_ms=round(tx["kernel_ms"], 4), alg_gbs=round(tx["alg_gbs"], 1),
+                              launch=tx["launch"],
                               speedup_vs_plain=round(tx["qps"] / tp["qps"], 4))
         log(f"finger {variant} timed: {tx}")
 
@@ -332,7 +355,8 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "ef_finger": op_f["ef"], "ef_plain": op_p["ef"],
-                   "recall_finger": round(tf["recall"], 4), "recall_plain": round(tp["recall"], 4)},
+                   "recall_finger": round(tf["recall"], 4), "recall_plain": round(tp["recall"], 4),
+                   "launch_finger": tf["launch"], "launch_plain": tp["launch"]},
         "plain_qps": round(tp["qps"], 1),
         "speedup_vs_plain": round(tf["qps"] / tp["qps"], 4),
         "plain_roofline": {"achieved": round(tp["alg_gbs"], 1), "frac": round(tp["alg_gbs"] / PEAK_HBM_GBS, 4),

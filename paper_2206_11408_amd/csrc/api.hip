@@ -100,7 +100,7 @@ int next_pow2(int x) {
 void free_tables(Tables* t) {
   if (t == nullptr) return;
   void* dev_ptrs[] = {t->data_owned, t->P, t->cc, t->pc, t->alpha, t->rho, t->codes, t->scale,
-                      t->piv_ids, t->qprep_B, t->qprep_Bnorm, t->samples, t->xy, t->gate_w,
+                      t->piv_ids, t->qprep_B, t->qprep_Bnorm, t->piv_b16, t->samples, t->xy, t->gate_w,
                       t->gate_b};
   for (void* p : dev_ptrs)
     if (p) (void)hipFree(p);
@@ -334,6 +334,10 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
       if ((st = dev_alloc(reinterpret_cast<void**>(&t->piv_ids), (size_t)t->npiv * 4, "pivots")) != FINGER_OK) return st;
       HIPCHK(hipMemcpyAsync(t->piv_ids, p->pivots, (size_t)t->npiv * 4, hipMemcpyDeviceToDevice, s));
       HIPCHK(launch_gather_rows(t->data, m, t->piv_ids, t->npiv, t->qprep_B + (size_t)rcols * m, s));
+      if ((st = dev_alloc(reinterpret_cast<void**>(&t->piv_b16),
+                          (size_t)pivot_pad_rows(t->npiv) * pivot_kpad(m) * 2, "bf16 pivots")) != FINGER_OK)
+        return st;
+      HIPCHK(launch_pack_pivots(t->qprep_B + (size_t)rcols * m, t->npiv, m, t->piv_b16, s));
     }
     HIPCHK(launch_row_norms(t->qprep_B, cols, m, t->qprep_Bnorm, s));
   }

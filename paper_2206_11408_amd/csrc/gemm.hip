@@ -96,13 +96,9 @@ __global__ void __launch_bounds__(256) k_gemm_store(const float* A, int64_t rows
       }
 }
 
-// Query prep: columns [0, rpad) of B are P (zero rows past r), columns
-// [rpad, rpad + npiv) are pivot vectors.  Stores Pq and, per 64-column tile,
-// the two best pivot scores |x|^2 - 2 q.x of each query.
-__global__ void __launch_bounds__(256) k_qprep(const float* Q, int64_t nq, const float* B,
-                                               const float* Bnorm, int cols, int K, int rpad,
-                                               int pcols, int pend, float* Pq, float2* best,
-                                               int ntiles) {
+// Pq = P q for a batch: B's first rpad rows are P (zero rows past r).
+__global__ void __launch_bounds__(256) k_qprep(const float* Q, int64_t nq, const float* B, int cols,
+                                               int K, int rpad, float* Pq) {
   __shared__ float As[BM * LDT], Bs[BN * LDT];
   const int64_t r0 = (int64_t)blockIdx.y * BM;
   const int64_t c0 = (int64_t)blockIdx.x * BN;
@@ -110,171 +106,166 @@ __global__ void __launch_bounds__(256) k_qprep(const float* Q, int64_t nq, const
   tile_mma(Q, nq, B, cols, K, r0, c0, As, Bs, acc);
   const int w = threadIdx.x / 64, l = threadIdx.x & 63;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  __syncthreads();
-  // scores to LDS (reuse As as a 64 x 65 tile)
-  float* Ct = As;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int rr = wr + 16 * i + 4 * (l >> 4) + v;
-        const int cl = wc + 16 * j + (l & 15);
-        const int64_t row = r0 + rr, col = c0 + cl;
-        const float c = acc[i][j][v];
-        if (col < rpad) {
-          if (row < nq) Pq[row * rpad + col] = c;
-        }
-        Ct[rr * 65 + cl] = (col >= pcols && col < pend) ? Bnorm[col] - 2.f * c
-                                                         : __int_as_float(0x7f800000);
+        const int64_t row = r0 + wr + 16 * i + 4 * (l >> 4) + v;
+        const int64_t col = c0 + wc + 16 * j + (l & 15);
+        if (col < rpad && row < nq) Pq[row * rpad + col] = acc[i][j][v];
       }
-  __syncthreads();
-  if (c0 + BN <= pcols || ntiles == 0) return;
-  // per query row: the best two (score, column) of this tile
-  const int tile = (int)(blockIdx.x) - pcols / BN;
-  for (int rr = w; rr < BM; rr += 4) {
-    const int64_t row = r0 + rr;
-    float s = Ct[rr * 65 + l];
-    int col = (int)c0 + l;
-    // min over the wave, ties to the smaller column
-    float s1 = s;
-    int c1 = col;
+}
+
+// ---------------------------------------------------------------- pivots
+// Entry choice by the nearest pivot, in two stages.
+//
+// Stage 1 (k_pivot_scores) ranks pivots by s = |p|^2 - 2 q.p on the bf16
+// matrix cores (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..+8)
+// and B[8(l/16)..+8)[l%16]; D[4(l/16)+v][l%16]).  Pivot rows were rounded to
+// bf16 once when the tables were built; query rows are rounded on load
+// (both exact for integers up to 256); products accumulate in float32.  One
+// wave owns 16 queries and one of kPivSplit pivot ranges, walks that range in
+// 16-pivot tiles, and keeps in every lane the lowest (score, pivot) of the
+// columns that land on it, so each query ends with kPivCand candidates (one
+// per lane stripe and range) without any cross-lane work in the loop.
+//
+// Stage 2 (k_qfinish, one wave per query) sorts the candidates by score and
+// re-ranks the best kPivRerank by exact float32 direct differences; the
+// nearest (ties to the smaller pivot index) becomes the entry.
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+constexpr int kPivSplit = 4;              // pivot ranges per 16-query tile
+constexpr int kPivCand = 16 * kPivSplit;  // candidates per query (= 64, one per lane)
+constexpr int kPivRerank = 16;            // candidates re-ranked exactly
+constexpr int kPivKs = 8;                 // 32-wide k-steps of a query held in registers
+
+static_assert(kPivCand == 64, "k_qfinish sorts one candidate per lane");
+
+// float -> unsigned with the same order (negative scores included)
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ b8v load_query_frag(const float* __restrict__ Q, int64_t nq, int m,
+                                              int64_t row, int k) {
+  float v[8];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      float so = __shfl_xor(s1, o, 64);
-      int co = __shfl_xor(c1, o, 64);
-      if (so < s1 || (so == s1 && co < c1)) { s1 = so; c1 = co; }
+  for (int e = 0; e < 8; ++e) v[e] = 0.f;
+  if (row < nq) {
+    const float* src = Q + row * (int64_t)m;
+    if (k < m) {
+      const float4 x = *reinterpret_cast<const float4*>(src + k);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
     }
-    float s2 = (col == c1) ? __int_as_float(0x7f800000) : s;
-    int c2 = col;
+    if (k + 4 < m) {
+      const float4 x = *reinterpret_cast<const float4*>(src + k + 4);
+      v[4] = x.x; v[5] = x.y; v[6] = x.z; v[7] = x.w;
+    }
+  }
+  b8v r;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      float so = __shfl_xor(s2, o, 64);
-      int co = __shfl_xor(c2, o, 64);
-      if (so < s2 || (so == s2 && co < c2)) { s2 = so; c2 = co; }
-    }
-    if (l == 0 && row < nq && tile >= 0) {
-      best[(row * ntiles + tile) * 2] = make_float2(s1, __int_as_float(c1));
-      best[(row * ntiles + tile) * 2 + 1] = make_float2(s2, __int_as_float(c2));
-    }
+  for (int e = 0; e < 8; ++e) r[e] = (__bf16)v[e];
+  return r;
+}
+
+// Fold one 16x16 score tile into the per-lane running minima.
+__device__ __forceinline__ void fold_tile(const f4v& acc, int col, int npiv,
+                                          const float* __restrict__ pnorm, uint64_t best[4]) {
+  if (col >= npiv) return;
+  const float pn = pnorm[col];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const uint64_t k = ((uint64_t)ordered_bits(pn - 2.f * acc[v]) << 32) | (uint32_t)col;
+    best[v] = k < best[v] ? k : best[v];
   }
 }
 
-// Pivot scores |x|^2 - 2 q.x on the bf16 matrix cores
-// (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..+8) and
-// B[8(l/16)..+8)[l%16]; D[4(l/16)+v][l%16]).  Queries and pivots are rounded
-// to bf16 (exact for integers up to 256), products accumulate in float32.
-// The scores only rank candidates: the final choice is re-ranked with exact
-// float32 distances in k_qfinish.  Per 64-column tile, each query keeps its
-// two best (score, column).
-typedef __bf16 b8v __attribute__((ext_vector_type(8)));
-constexpr int PK = 32, PLD = 40;  // K slab and padded LDS row (bf16 elements)
-
-__global__ void __launch_bounds__(256) k_pivot_scores(const float* Q, int64_t nq, const float* B,
-                                                      const float* Bnorm, int pcols, int pend,
-                                                      int K, float2* best, int ntiles) {
-  __shared__ __align__(16) __bf16 As[BM * PLD], Bs[BN * PLD];
-  __shared__ float Ct[BM * 65];
-  const int64_t r0 = (int64_t)blockIdx.y * BM;
-  const int tile = blockIdx.x;
-  const int64_t c0 = pcols + (int64_t)tile * BN;
-  const int w = threadIdx.x / 64, l = threadIdx.x & 63;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  f4v acc[2][2];
+// grid: ceil(nq / 16) * kPivSplit waves, 4 per block; PB [npad][kpad] bf16,
+// npad = kPivSplit * range, rows >= npiv zero; cand [nq][kPivCand].
+// KS: 32-wide k-steps (kpad = 32 KS) when the query fits in registers
+// (KS <= kPivKs); KS = 0 is the general path that streams the query in
+// chunks of kPivKs steps.  The pivot tile of the next iteration is loaded
+// while the current one is multiplied (two register sets).
+template <int KS>
+__global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ Q, int64_t nq, int m,
+                                                      const __bf16* __restrict__ PB,
+                                                      const float* __restrict__ pnorm, int npiv,
+                                                      int kpad, int range,
+                                                      uint64_t* __restrict__ cand) {
+  const int64_t wid = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int64_t q0 = (wid / kPivSplit) * 16;
+  const int split = (int)(wid % kPivSplit);
+  if (q0 >= nq) return;  // whole waves only
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lk = 8 * (l >> 4);
+  const int c_beg = split * range;
+  uint64_t best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
+  if constexpr (KS > 0) {
+    b8v a[KS];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < KS; ++i) a[i] = load_query_frag(Q, nq, m, q0 + lr, 32 * i + lk);
+    const __bf16* base = PB + (int64_t)(c_beg + lr) * kpad + lk;
+    b8v bx[KS], by[KS];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += PK) {
-    __syncthreads();
-    // stage: 64 rows x 32 k of each operand, 8 elements per thread
-    {
-      const int row = threadIdx.x >> 2, kc = (threadIdx.x & 3) * 8;
-      float va[8], vb[8];
+    for (int i = 0; i < KS; ++i) bx[i] = *reinterpret_cast<const b8v*>(base + 32 * i);
+    // range is a multiple of 16: tiles t = 0, 16, ...; bx holds tile t, by tile t + 16
+    for (int t = 0; t < range; t += 32) {
+      const bool has_y = t + 16 < range;
+      if (has_y) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) { va[e] = 0.f; vb[e] = 0.f; }
-      if (k0 + kc < K) {  // K % 4 == 0 and slabs of 8 never straddle K when K % 8 == 0
-        const int64_t qa = r0 + row, cb = c0 + row;
+        for (int i = 0; i < KS; ++i)
+          by[i] = *reinterpret_cast<const b8v*>(base + (int64_t)(t + 16) * kpad + 32 * i);
+      }
+      f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int e = 0; e < 8; e += 4) {
-          if (k0 + kc + e < K) {
-            if (qa < nq) {
-              const float4 v = *reinterpret_cast<const float4*>(Q + qa * K + k0 + kc + e);
-              va[e] = v.x; va[e + 1] = v.y; va[e + 2] = v.z; va[e + 3] = v.w;
-            }
-            if (cb < pend) {
-              const float4 v = *reinterpret_cast<const float4*>(B + cb * K + k0 + kc + e);
-              vb[e] = v.x; vb[e + 1] = v.y; vb[e + 2] = v.z; vb[e + 3] = v.w;
-            }
+      for (int i = 0; i < KS; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bx[i], acc, 0, 0, 0);
+      fold_tile(acc, c_beg + t + lr, npiv, pnorm, best);
+      if (!has_y) break;
+      if (t + 32 < range) {
+#pragma unroll
+        for (int i = 0; i < KS; ++i)
+          bx[i] = *reinterpret_cast<const b8v*>(base + (int64_t)(t + 32) * kpad + 32 * i);
+      }
+      acc = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < KS; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], by[i], acc, 0, 0, 0);
+      fold_tile(acc, c_beg + t + 16 + lr, npiv, pnorm, best);
+    }
+  } else {
+    const int ksteps = kpad / 32;
+    b8v a[kPivKs], b[kPivKs];
+    for (int t = 0; t < range; t += 16) {
+      f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
+      for (int c = 0; c < ksteps; c += kPivKs) {
+#pragma unroll
+        for (int i = 0; i < kPivKs; ++i) {
+          if (c + i < ksteps) {
+            a[i] = load_query_frag(Q, nq, m, q0 + lr, 32 * (c + i) + lk);
+            b[i] = *reinterpret_cast<const b8v*>(PB + (int64_t)(c_beg + t + lr) * kpad + 32 * (c + i) + lk);
           }
         }
-      }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        As[row * PLD + kc + e] = (__bf16)va[e];
-        Bs[row * PLD + kc + e] = (__bf16)vb[e];
+        for (int i = 0; i < kPivKs; ++i)
+          if (c + i < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[i], acc, 0, 0, 0);
       }
+      fold_tile(acc, c_beg + t + lr, npiv, pnorm, best);
     }
-    __syncthreads();
-    b8v a[2], b[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-      a[i] = *reinterpret_cast<const b8v*>(&As[(wr + 16 * i + (l & 15)) * PLD + 8 * (l >> 4)]);
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      b[j] = *reinterpret_cast<const b8v*>(&Bs[(wc + 16 * j + (l & 15)) * PLD + 8 * (l >> 4)]);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rr = wr + 16 * i + 4 * (l >> 4) + v;
-        const int cl = wc + 16 * j + (l & 15);
-        const int64_t col = c0 + cl;
-        Ct[rr * 65 + cl] = col < pend ? Bnorm[col] - 2.f * acc[i][j][v] : __int_as_float(0x7f800000);
-      }
-  __syncthreads();
-  for (int rr = w; rr < BM; rr += 4) {
-    const int64_t row = r0 + rr;
-    const float s = Ct[rr * 65 + l];
-    const int col = (int)c0 + l;
-    float s1 = s;
-    int c1 = col;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const float so = __shfl_xor(s1, o, 64);
-      const int co = __shfl_xor(c1, o, 64);
-      if (so < s1 || (so == s1 && co < c1)) { s1 = so; c1 = co; }
-    }
-    float s2 = (col == c1) ? __int_as_float(0x7f800000) : s;
-    int c2 = col;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const float so = __shfl_xor(s2, o, 64);
-      const int co = __shfl_xor(c2, o, 64);
-      if (so < s2 || (so == s2 && co < c2)) { s2 = so; c2 = co; }
-    }
-    if (l == 0 && row < nq) {
-      best[(row * ntiles + tile) * 2] = make_float2(s1, __int_as_float(c1));
-      best[(row * ntiles + tile) * 2 + 1] = make_float2(s2, __int_as_float(c2));
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = q0 + 4 * (l >> 4) + v;
+    if (row < nq) cand[row * kPivCand + split * 16 + lr] = best[v];
   }
 }
 
-// Per query (one wave): norms, then among the per-tile best pivot scores
-// the 8 lowest are re-ranked by exact direct differences; the nearest
-// pivot (ties to the smaller pivot index) becomes the entry.
-__global__ void k_qfinish(const float* Q, int64_t nq, int m, const float* B, int pcols,
-                          const int32_t* piv_ids, int npiv, const float2* best, int ntiles,
-                          float* qq, int32_t* entries) {
+// Per query (one wave): |q|^2, then (with candidates) the exact re-rank.
+// PF: float32 pivot rows [npiv][m].
+__global__ void k_qfinish(const float* __restrict__ Q, int64_t nq, int m,
+                          const float* __restrict__ PF, const int32_t* __restrict__ piv_ids,
+                          int npiv, const uint64_t* __restrict__ cand, float* __restrict__ qq,
+                          int32_t* __restrict__ entries) {
   const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (q >= nq) return;
   const int l = threadIdx.x & 63;
@@ -283,50 +274,40 @@ __global__ void k_qfinish(const float* Q, int64_t nq, int m, const float* B, int
   for (int j = l; j < m; j += 64) acc += qv[j] * qv[j];
   acc = wave_sum(acc);
   if (l == 0) qq[q] = acc;
-  if (ntiles == 0 || entries == nullptr) return;
-  // 4 best candidates by score (each lane scans a strided subset)
-  float cs[4];
-  int cc[4];
-  for (int i = 0; i < 4; ++i) { cs[i] = __int_as_float(0x7f800000); cc[i] = 0x7fffffff; }
-  for (int i = l; i < 2 * ntiles; i += 64) {
-    float2 b = best[q * 2 * ntiles + i];
-    float s = b.x;
-    int c = __float_as_int(b.y);
-    if (!(s < __int_as_float(0x7f800000))) continue;
-    // insert into the lane's sorted 4-list
-    for (int t = 0; t < 4; ++t) {
-      if (s < cs[t] || (s == cs[t] && c < cc[t])) {
-        float ts = cs[t]; int tc = cc[t];
-        cs[t] = s; cc[t] = c; s = ts; c = tc;
-      }
+  if (cand == nullptr || entries == nullptr) return;
+  const uint64_t key = bitonic_sort<64>(cand[q * kPivCand + l]);
+  // four lanes per candidate; candidate ci is the ci-th lowest score
+  const int ci = l >> 2, part = l & 3;
+  const uint64_t ck = shfl_u64(key, ci);
+  const int col = (int)(uint32_t)ck;
+  const bool valid = ck != ~0ull && col >= 0 && col < npiv;
+  float d = 0.f;
+  if (valid) {
+    const float4* p4 = reinterpret_cast<const float4*>(PF + (int64_t)col * m);
+    const float4* q4 = reinterpret_cast<const float4*>(qv);
+    for (int j = part; j < m / 4; j += 4) {
+      const float4 x = q4[j], y = p4[j];
+      const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z, dw = x.w - y.w;
+      d += dx * dx + dy * dy + dz * dz + dw * dw;
     }
   }
-  float bestd = __int_as_float(0x7f800000);
-  int bestc = 0x7fffffff;
-  for (int round = 0; round < 8; ++round) {
-    // wave-wide minimum of the lanes' heads
-    float s1 = cs[0];
-    int c1 = cc[0];
-    for (int o = 32; o >= 1; o >>= 1) {
-      float so = __shfl_xor(s1, o, 64);
-      int co = __shfl_xor(c1, o, 64);
-      if (so < s1 || (so == s1 && co < c1)) { s1 = so; c1 = co; }
-    }
-    if (!(s1 < __int_as_float(0x7f800000))) break;
-    if (cc[0] == c1) {  // pop the head
-      for (int t = 0; t < 3; ++t) { cs[t] = cs[t + 1]; cc[t] = cc[t + 1]; }
-      cs[3] = __int_as_float(0x7f800000); cc[3] = 0x7fffffff;
-    }
-    // exact distance to pivot column c1
-    const float* pv = B + (int64_t)c1 * m;
-    float d = 0.f;
-    for (int j = l; j < m; j += 64) { float t = qv[j] - pv[j]; d += t * t; }
-    d = wave_sum(d);
-    const int pidx = c1 - pcols;
-    if (d < bestd || (d == bestd && pidx < bestc)) { bestd = d; bestc = pidx; }
+  d += shfl_xor_f(d, 1);
+  d += shfl_xor_f(d, 2);
+  uint64_t mine = (valid && ci < kPivRerank) ? make_key(d, col) : ~0ull;
+#pragma unroll
+  for (int o = 4; o < 64; o <<= 1) {
+    const uint64_t other = shfl_xor_u64(mine, o);
+    mine = other < mine ? other : mine;
   }
-  if (bestc < 0 || bestc >= npiv) bestc = 0;  // only for non-finite scores
-  if (l == 0) entries[q] = piv_ids[bestc];
+  if (l == 0) entries[q] = piv_ids[mine == ~0ull ? 0 : key_id(mine)];
+}
+
+__global__ void k_pack_bf16_rows(const float* __restrict__ src, int rows, int m, int rows_pad,
+                                 int kpad, __bf16* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows_pad * kpad) return;
+  const int row = (int)(i / kpad), k = (int)(i % kpad);
+  dst[i] = (__bf16)((row < rows && k < m) ? src[(int64_t)row * m + k] : 0.f);
 }
 
 }  // namespace
@@ -340,36 +321,55 @@ hipError_t launch_gemm_nt(const float* A, int64_t rows, const float* B, int64_t 
 }
 
 size_t query_prep_scratch_bytes(const Tables& t, int64_t nq) {
-  const int ntiles = t.npiv > 0 ? (t.npiv + BN - 1) / BN : 0;
-  return (size_t)nq * ntiles * 2 * sizeof(float2);
+  return t.npiv > 0 ? (size_t)nq * kPivCand * sizeof(uint64_t) : 0;
+}
+
+int pivot_pad_rows(int npiv) { return (npiv + 16 * kPivSplit - 1) / (16 * kPivSplit) * (16 * kPivSplit); }
+int pivot_kpad(int m) { return (m + 31) / 32 * 32; }
+
+hipError_t launch_pack_pivots(const float* src, int npiv, int m, __bf16* dst, hipStream_t s) {
+  const int rows_pad = pivot_pad_rows(npiv), kpad = pivot_kpad(m);
+  const int64_t total = (int64_t)rows_pad * kpad;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_bf16_rows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src,
+                     npiv, m, rows_pad, kpad, dst);
+  return hipGetLastError();
 }
 
 hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float* qq, float* Pq,
-                             int32_t* entries, float* scratch, hipStream_t s, bool need_pq) {
+                             int32_t* entries, void* scratch, hipStream_t s, bool need_pq) {
   if (nq == 0) return hipSuccess;
   const int rpad = rpad_of(t.r);
   const int rcols = (rpad + BN - 1) / BN * BN;  // P block padded to whole tiles
-  const int ntiles = t.npiv > 0 ? (t.npiv + BN - 1) / BN : 0;
-  float2* best = reinterpret_cast<float2*>(scratch);
+  const bool piv = t.npiv > 0 && entries != nullptr;
+  uint64_t* cand = piv ? reinterpret_cast<uint64_t*>(scratch) : nullptr;
   if (t.r > 0 && need_pq) {
     // Pq = P q in float32 MFMA (the estimate needs full precision)
     dim3 grid((unsigned)(rcols / BN), (unsigned)((nq + BM - 1) / BM));
-    hipLaunchKernelGGL(k_qprep, grid, dim3(256), 0, s, Q, nq, t.qprep_B, t.qprep_Bnorm, rcols, t.m,
-                       rpad, rcols, rcols, Pq, best, 0);
+    hipLaunchKernelGGL(k_qprep, grid, dim3(256), 0, s, Q, nq, t.qprep_B, rcols, t.m, rpad, Pq);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (ntiles > 0) {
-    dim3 grid((unsigned)ntiles, (unsigned)((nq + BM - 1) / BM));
-    hipLaunchKernelGGL(k_pivot_scores, grid, dim3(256), 0, s, Q, nq, t.qprep_B, t.qprep_Bnorm,
-                       rcols, rcols + t.npiv, t.m, best, ntiles);
+  if (piv) {
+    const int64_t waves = (nq + 15) / 16 * kPivSplit;
+    const int range = pivot_pad_rows(t.npiv) / kPivSplit;
+    const int kpad = pivot_kpad(t.m);
+    const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+    const float* pn = t.qprep_Bnorm + rcols;
+    switch (kpad / 32) {
+      case 1: hipLaunchKernelGGL(k_pivot_scores<1>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
+      case 2: hipLaunchKernelGGL(k_pivot_scores<2>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
+      case 3: hipLaunchKernelGGL(k_pivot_scores<3>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
+      case 4: hipLaunchKernelGGL(k_pivot_scores<4>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
+      default: hipLaunchKernelGGL(k_pivot_scores<0>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   const int wpb = 4;
   hipLaunchKernelGGL(k_qfinish, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), 0, s, Q,
-                     nq, t.m, t.qprep_B, rcols, t.piv_ids, t.npiv, best, ntiles, qq,
-                     ntiles > 0 ? entries : nullptr);
+                     nq, t.m, t.qprep_B + (int64_t)rcols * t.m, t.piv_ids, t.npiv, cand, qq,
+                     piv ? entries : nullptr);
   return hipGetLastError();
 }
 

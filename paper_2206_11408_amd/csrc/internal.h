@@ -47,6 +47,7 @@ struct Tables {
   int32_t npiv = 0;
   int32_t* piv_ids = nullptr;      // [npiv]
   float* qprep_B = nullptr;        // [(r + npiv) rounded up to 64][m]
+  __bf16* piv_b16 = nullptr;       // [pivot_pad_rows(npiv)][pivot_kpad(m)] pivots in bf16, zero padded
   float* qprep_Bnorm = nullptr;    // [(r + npiv) rounded up to 64]  (|row|^2)
   int32_t qprep_cols = 0;          // r + npiv rounded up to 64
   // distribution matching constants
@@ -75,8 +76,12 @@ hipError_t launch_gemm_nt(const float* A, int64_t rows, const float* B, int64_t 
 // query preparation: qq[i] = |q_i|^2, Pq[i][0..r) = P q_i, and (if npiv > 0)
 // entries[i] = nearest pivot id by exact squared distance
 hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float* qq, float* Pq,
-                             int32_t* entries, float* scratch, hipStream_t s, bool need_pq = true);
+                             int32_t* entries, void* scratch, hipStream_t s, bool need_pq = true);
 size_t query_prep_scratch_bytes(const Tables& t, int64_t nq);
+// bf16 copy of the pivot rows for the query-prep scoring kernel
+int pivot_pad_rows(int npiv);
+int pivot_kpad(int m);
+hipError_t launch_pack_pivots(const float* src, int npiv, int m, __bf16* dst, hipStream_t s);
 
 struct SearchLaunch {
   const float* queries;

@@ -29,13 +29,19 @@ def _key(tables: api.Tables, mode: int, ef_max: int, mixed: bool) -> str:
             f"code{inf['code_type']}|mode{mode}|ef{ef_max}|mixed{int(mixed)}")
 
 
-def candidates(mode: int):
+def candidates(mode: int, ef_max: int = 64):
+    # visited-set capacity trades LDS per wave (resident waves) against probe
+    # length; the default is next_pow2(24 ef_max) clamped to [1024, 8192]
+    vis_default = min(8192, max(1024, 1 << (24 * ef_max - 1).bit_length()))
+    vis = sorted({vis_default, max(512, vis_default // 2)})
     out = []
-    for wpc in (4, 8, 12, 16, 24, 32):
+    for wpc in (8, 12, 16, 20, 24, 32):
         for persistent in (0, 1):
             pfs = (0,) if mode == L.MODE_PLAIN else (-1, 1)
             for pf in pfs:
-                out.append({"waves_per_cu": wpc, "persistent": persistent, "code_prefetch": pf})
+                for vc in vis:
+                    out.append({"waves_per_cu": wpc, "persistent": persistent, "code_prefetch": pf,
+                                "visited_capacity": vc})
     return out
 
 
@@ -60,7 +66,7 @@ def autotune(tables: api.Tables, queries: torch.Tensor, base: dict, repeats: int
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     timings = []
-    for cand in candidates(mode):
+    for cand in candidates(mode, ef_max):
         p = api.search_params(**{**base, **cand})
         try:
             api.finger_search(tables, queries, p)
