@@ -459,14 +459,12 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
     return fail(FINGER_EINVAL, "code_prefetch = %d must be -1, 0 or 1", p->code_prefetch);
   if (vis_cap < 256 || (vis_cap & (vis_cap - 1)) != 0)
     return fail(FINGER_EINVAL, "visited_capacity = %d must be a power of two >= 256", vis_cap);
-  const int gate_h = p->mode == FINGER_MODE_GATED ? t->gate_h : 0;
   const int gate_in = p->mode == FINGER_MODE_GATED ? t->gate_in : 0;
   const int r_used = p->mode == FINGER_MODE_PLAIN ? 0 : t->r;
-  const int lds_wave = search_lds_bytes(ef_max, vis_cap, r_used, t->m, 0, gate_in);
-  const int lds_shared = search_lds_bytes(0, 0, r_used, t->m, gate_h, gate_in) -
-                         search_lds_bytes(0, 0, r_used, t->m, 0, gate_in);
+  const int lds_wave = search_lds_bytes(ef_max, vis_cap, r_used, t->m, gate_in);
+  const int lds_shared = 0;
   const int lds_limit = 160 * 1024;
-  const int wpb = p->mode == FINGER_MODE_GATED ? 4 : 1;
+  const int wpb = 1;
   if (lds_shared + wpb * lds_wave > lds_limit)
     return fail(FINGER_EOVERFLOW, "per-wave LDS of %d bytes (ef_max %d, visited %d) exceeds the CU budget", lds_wave, ef_max, vis_cap);
   int per_cu = p->waves_per_cu;
@@ -681,11 +679,11 @@ int finger_gate_attach(finger_tables* th, const float* weights, int32_t in_dim, 
   int st = dev_alloc(reinterpret_cast<void**>(&wd.p), (size_t)P * 4, "gate weights");
   if (st != FINGER_OK) return st;
   HIPCHK(hipMemcpy(wd.p, weights, (size_t)P * 4, hipMemcpyHostToDevice));
-  const int64_t nw = (int64_t)hidden * in_dim + (int64_t)hidden * hidden + hidden;
+  const GateLayout gl = gate_layout(t->r, hidden);
   uint16_t* wbf = nullptr;
   float* b = nullptr;
-  if ((st = dev_alloc(reinterpret_cast<void**>(&wbf), (size_t)nw * 2, "gate bf16 weights")) != FINGER_OK) return st;
-  if ((st = dev_alloc(reinterpret_cast<void**>(&b), (size_t)(2 * hidden + 1) * 4, "gate biases")) != FINGER_OK) {
+  if ((st = dev_alloc(reinterpret_cast<void**>(&wbf), (size_t)gl.total * 2, "gate bf16 weights")) != FINGER_OK) return st;
+  if ((st = dev_alloc(reinterpret_cast<void**>(&b), (size_t)(2 * gl.hp + 1) * 4, "gate biases")) != FINGER_OK) {
     (void)hipFree(wbf);
     return st;
   }

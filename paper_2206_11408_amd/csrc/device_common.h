@@ -62,6 +62,12 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
   int hi = __shfl((int)(uint32_t)(v >> 32), src, 64);
   return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
+// v from a wave-uniform lane (scalar result)
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   int lo = __shfl_xor((int)(uint32_t)v, m, 64);
   int hi = __shfl_xor((int)(uint32_t)(v >> 32), m, 64);

@@ -183,32 +183,45 @@ __global__ void k_adam(float* w, const float* g, float* m1, float* m2, int64_t c
   w[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
-// bf16 weights for the search kernel, transposed so that one lane per
-// hidden unit reads consecutive addresses: W1T [in][H], W2T [H][H], W3 [H]
+// bf16 weights for the search kernel (layout GateLayout, hidden units
+// padded to Hp with zero weights and biases):
+//   W1s [r][Hp]   first-layer columns of the shared query features w/|w|,
+//                 transposed so that one lane per hidden unit reads in order
+//   W1e [Hp][K1]  first-layer columns of the per-edge features, row-major
+//                 and zero padded to K1 = 32 ceil((r + 4) / 32) (MFMA B tiles)
+//   W2  [Hp][K2]  second layer, zero padded to K2 = 32 ceil(Hp / 32)
+//   W3  [Hp]
+// biases (float): b1 [Hp], b2 [Hp], b3
 __global__ void k_pack_gate(const float* w, int in, int H, uint16_t* wbf, float* b) {
   const Off o = offsets(in, H);
-  const int64_t n1 = (int64_t)H * in, n2 = (int64_t)H * H;
-  const int64_t nw = n1 + n2 + H;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+  const GateLayout L = gate_layout((in - 4) / 2, H);
+  const int r = L.r;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    float v;
-    if (i < n1) {
-      const int64_t inp = i / H, hid = i % H;  // W1T[inp][hid] = W1[hid][inp]
-      v = w[o.w1 + hid * in + inp];
-    } else if (i < n1 + n2) {
-      const int64_t k = i - n1, inp = k / H, hid = k % H;
-      v = w[o.w2 + hid * H + inp];
+    float v = 0.f;
+    if (i < L.w1e) {
+      const int inp = (int)(i / L.hp), hid = (int)(i % L.hp);  // W1s[inp][hid] = W1[hid][inp]
+      if (hid < H) v = w[o.w1 + (int64_t)hid * in + inp];
+    } else if (i < L.w2) {
+      const int64_t k = i - L.w1e;
+      const int hid = (int)(k / L.k1), c = (int)(k % L.k1);
+      if (hid < H && c < r + 4) v = w[o.w1 + (int64_t)hid * in + r + c];
+    } else if (i < L.w3) {
+      const int64_t k = i - L.w2;
+      const int hid = (int)(k / L.k2), c = (int)(k % L.k2);
+      if (hid < H && c < H) v = w[o.w2 + (int64_t)hid * H + c];
     } else {
-      v = w[o.w3 + (i - n1 - n2)];
+      const int hid = (int)(i - L.w3);
+      if (hid < H) v = w[o.w3 + hid];
     }
     wbf[i] = (uint16_t)(__float_as_uint(rbf(v)) >> 16);
   }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < H) {
-    b[i] = w[o.b1 + i];
-    b[H + i] = w[o.b2 + i];
+  if (i < L.hp) {
+    b[i] = i < H ? w[o.b1 + i] : 0.f;
+    b[L.hp + i] = i < H ? w[o.b2 + i] : 0.f;
   }
-  if (i == 0) b[2 * H] = w[o.b3];
+  if (i == 0) b[2 * L.hp] = w[o.b3];
 }
 
 // cos(q_res, d_res) from a logged row through Eq. 2

@@ -23,6 +23,26 @@ constexpr int kDefaultSamples = 100000;
 // padded to a multiple of 32 (one 32-element chunk per lane in the search).
 inline int rpad_of(int r) { return (r + 31) / 32 * 32; }
 
+// Packed bf16 gate weights (element offsets): W1s [r][hp] | W1e [hp][k1] |
+// W2 [hp][k2] | W3 [hp]; hp = hidden rounded up to 16 (MFMA tile), k1 =
+// r + 4 rounded up to 32, k2 = hp rounded up to 32.
+struct GateLayout {
+  int r, hp, k1, k2;
+  int64_t w1e, w2, w3, total;
+};
+__host__ __device__ inline GateLayout gate_layout(int r, int hidden) {
+  GateLayout L;
+  L.r = r;
+  L.hp = (hidden + 15) / 16 * 16;
+  L.k1 = (r + 4 + 31) / 32 * 32;
+  L.k2 = (L.hp + 31) / 32 * 32;
+  L.w1e = (int64_t)r * L.hp;
+  L.w2 = L.w1e + (int64_t)L.hp * L.k1;
+  L.w3 = L.w2 + (int64_t)L.hp * L.k2;
+  L.total = L.w3 + L.hp;
+  return L;
+}
+
 struct Tables {
   int device = 0;
   int64_t n = 0;
@@ -60,8 +80,8 @@ struct Tables {
   int gate = 0;
   int32_t gate_in = 0, gate_h = 0;
   double eps_gate = 0;
-  uint16_t* gate_w = nullptr;      // bf16 weights, layout of finger_gate_attach
-  float* gate_b = nullptr;         // float biases b1 [H], b2 [H], b3 [1]
+  uint16_t* gate_w = nullptr;      // bf16 weights packed as GateLayout
+  float* gate_b = nullptr;         // float biases b1 [hp], b2 [hp], b3 [1]
 };
 
 // ------------------------------------------------------------ launchers
@@ -110,7 +130,7 @@ struct SearchLaunch {
 };
 hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s);
 bool search_prefetch_supported(const Tables& t);
-int search_lds_bytes(int ef_max, int vis_cap, int r, int m, int gate_h, int gate_in);
+int search_lds_bytes(int ef_max, int vis_cap, int r, int m, int gate_in);
 
 hipError_t launch_estimate_edges(const Tables& t, const float* Q, const float* qq,
                                  const float* Pq, const int32_t* qi, const int32_t* ci,

@@ -244,18 +244,19 @@ __device__ __forceinline__ void load_query(const KArgs& a, int64_t qi, float4* q
 }
 
 // exact squared distances of the `cnt` ids in ids_lds[0..cnt) to the query;
-// results go to d_lds[0..cnt).  G lanes share one vector; NP passes of
-// 64/G vectors are in flight together.
+// lane l (l < cnt) receives the distance of ids_lds[l].  G lanes share one
+// vector; NP groups of 64/G vectors are in flight together; each group sum
+// is handed to its lane by a cross-lane read (no LDS round trip).
 // qv: the query chunks this lane needs, either in registers or (qlds) read
 // from the wave's LDS copy of the query when needed
 template <int G, int T4, int NP>
-__device__ __forceinline__ void exact_dists(const KArgs& a, const float4* qv, const float4* qlds,
-                                            const int* __restrict__ ids_lds, int cnt,
-                                            float* __restrict__ d_lds) {
+__device__ __forceinline__ float exact_dists(const KArgs& a, const float4* qv, const float4* qlds,
+                                             const int* __restrict__ ids_lds, int cnt) {
   constexpr int NPP = 64 / G;
   const int l = lane_id();
   const int lg = l & (G - 1);
   const int slot = l / G;
+  float mine = 0.f;
   for (int p0 = 0; p0 < cnt; p0 += NP * NPP) {
     float4 xv[NP][T4];
     int p[NP];
@@ -287,40 +288,93 @@ __device__ __forceinline__ void exact_dists(const KArgs& a, const float4* qv, co
         acc += dx * dx + dy * dy + dz * dz + dw * dw;
       }
       acc = group_sum<G>(acc);
-      if (lg == 0 && p[h] < cnt) d_lds[p[h]] = acc;
+      // vector p0 + h NPP + s sits in lanes [s G, s G + G); lane p0 + h NPP + s takes it
+      const int want = l - p0 - h * NPP;
+      const float got = __shfl(acc, (want >= 0 && want < NPP ? want : 0) * G, 64);
+      if (want >= 0 && want < NPP) mine = got;
     }
   }
-  wave_lds_sync();
+  return mine;
 }
 
-// Gate network on one edge: every lane owns one hidden unit (lanes >= H
-// idle).  base1 = b1 + W1[:, 0:r] (w/|w|) is shared by the expansion's
-// edges; u (r floats) and the 4 scalars s are this edge's features in LDS.
-__device__ __forceinline__ float gate_edge(const KArgs& a, const uint16_t* __restrict__ W,
-                                           const float* __restrict__ B, float base1,
-                                           const float* __restrict__ u, const float* s,
-                                           float* __restrict__ hbuf) {
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  return (uint16_t)(__float_as_uint(round_bf16(f)) >> 16);
+}
+__device__ __forceinline__ b8v ld_b8(const uint16_t* p) { return *reinterpret_cast<const b8v*>(p); }
+
+// The gate network on E <= 32 edges whose features (bf16, zero padded to
+// k1 columns) are rows of featb: 16-row tiles through the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..+8) and
+// B[8(l/16)..+8)[l%16]; D[4(l/16)+v][l%16]), float32 accumulation, hidden
+// activations rounded to bf16 after the ReLU (the training kernels' rule).
+// b1v[nt] is b1 + W1[:, 0:r] w/|w| for hidden unit 16 nt + l%16 (shared by
+// the expansion's edges).  Writes yv[0..E).
+__device__ __forceinline__ void gate_tiles(const GateLayout& GL, const uint16_t* __restrict__ W,
+                                           const float* __restrict__ B, const float b1v[4],
+                                           const uint16_t* __restrict__ featb,
+                                           uint16_t* __restrict__ h1b, float* __restrict__ yv,
+                                           int E) {
   const int l = lane_id();
-  const int H = a.gate_h, r = a.r;
-  const uint16_t* W1T = W;                           // [in][H]
-  const uint16_t* W2T = W + (int64_t)a.gate_in * H;  // [H][H]
-  const uint16_t* W3 = W2T + H * H;                  // [H]
-  float z = base1;
-  if (l < H) {
-    for (int i = 0; i < r; ++i) z += bf16_to_f(W1T[(r + i) * H + l]) * u[i];
+  const int lr = l & 15, lk = 8 * (l >> 4), g = l >> 4;
+  const int NT = GL.hp / 16;
+  const uint16_t* W1e = W + GL.w1e;
+  const uint16_t* W2 = W + GL.w2;
+  const uint16_t* W3 = W + GL.w3;
+  for (int mt = 0; 16 * mt < E; ++mt) {
+    f4v acc[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) z += bf16_to_f(W1T[(2 * r + c) * H + l]) * s[c];
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < GL.k1 / 32; ++ks) {
+      const b8v A = ld_b8(featb + (16 * mt + lr) * GL.k1 + 32 * ks + lk);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        if (nt < NT)
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              A, ld_b8(W1e + (16 * nt + lr) * GL.k1 + 32 * ks + lk), acc[nt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      if (nt < NT)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          h1b[(16 * mt + 4 * g + v) * GL.k2 + 16 * nt + lr] = bf16_bits(fmaxf(acc[nt][v] + b1v[nt], 0.f));
+    wave_lds_sync();
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < GL.k2 / 32; ++ks) {
+      const b8v A = ld_b8(h1b + (16 * mt + lr) * GL.k2 + 32 * ks + lk);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        if (nt < NT)
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              A, ld_b8(W2 + (16 * nt + lr) * GL.k2 + 32 * ks + lk), acc[nt], 0, 0, 0);
+    }
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      if (nt < NT) {
+        const float w3 = bf16_to_f(W3[16 * nt + lr]);
+        const float b2 = B[GL.hp + 16 * nt + lr];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[v] += w3 * round_bf16(fmaxf(acc[nt][v] + b2, 0.f));
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) part[v] += shfl_xor_f(part[v], o);
+    if (lr == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * mt + 4 * g + v;
+        if (row < E) yv[row] = part[v] + B[2 * GL.hp];
+      }
+    }
+    wave_lds_sync();
   }
-  const float h1 = l < H ? round_bf16(fmaxf(z, 0.f)) : 0.f;
-  hbuf[l] = h1;
-  wave_lds_sync();
-  float z2 = l < H ? B[H + l] : 0.f;
-  if (l < H)
-    for (int i = 0; i < H; ++i) z2 += bf16_to_f(W2T[i * H + l]) * hbuf[i];
-  const float h2 = l < H ? round_bf16(fmaxf(z2, 0.f)) : 0.f;
-  const float y = wave_sum(l < H ? bf16_to_f(W3[l]) * h2 : 0.f) + B[2 * H];
-  wave_lds_sync();
-  return y;
 }
 
 template <int MODE, int CODE, int G, int T4, bool PREFETCH>
@@ -336,10 +390,8 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   tD[1] = reinterpret_cast<float*>(base + 8 * a.ef_max);
   tI[1] = reinterpret_cast<int*>(base + 12 * a.ef_max);
   int* vis = reinterpret_cast<int*>(base + 16 * a.ef_max);
-  uint64_t* ck = reinterpret_cast<uint64_t*>(base + 16 * a.ef_max + 4 * a.vis_cap);
-  int* cid = reinterpret_cast<int*>(ck + 64);
-  float* cd = reinterpret_cast<float*>(cid + 64);
-  int* cflag = reinterpret_cast<int*>(cd + 64);
+  int* cid = reinterpret_cast<int*>(base + 16 * a.ef_max + 4 * a.vis_cap);
+  int* cflag = reinterpret_cast<int*>(cid + 64);
   float* wv = reinterpret_cast<float*>(cflag + 64);  // [rpad] (screening)
   float* pqv = wv + a.rpad;                          // [rpad] this query's Pq
   float4* qsh = reinterpret_cast<float4*>(pqv + a.rpad);  // [m] the query (screening modes)
@@ -350,15 +402,23 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
 
   const uint16_t* gw = nullptr;
   const float* gb = nullptr;
+  GateLayout GL{};
+  uint16_t* featb = nullptr;  // gated: per-wave edge features [32][k1] bf16
+  uint16_t* h1b = nullptr;    // gated: hidden activations [32][k2] bf16
+  float* yv = nullptr;        // gated: outputs [32]
   if constexpr (MODE == FINGER_MODE_GATED) {
-    uint16_t* sw = reinterpret_cast<uint16_t*>(smem);
-    const int nw = a.gate_h * a.gate_in + a.gate_h * a.gate_h + a.gate_h;
-    for (int i = threadIdx.x; i < nw; i += blockDim.x) sw[i] = a.gate_w[i];
-    float* sb = reinterpret_cast<float*>(smem + ((2 * nw + 15) & ~15));
-    for (int i = threadIdx.x; i < 2 * a.gate_h + 1; i += blockDim.x) sb[i] = a.gate_b[i];
-    __syncthreads();
-    gw = sw;
-    gb = sb;
+    // the packed weights (about 29 KB at r = 64, 64 hidden units) are read
+    // through the caches: every wave of the CU reads the same lines, and
+    // LDS stays with the per-query state (more resident waves)
+    GL = gate_layout(a.r, a.gate_h);
+    gw = a.gate_w;
+    gb = a.gate_b;
+    featb = reinterpret_cast<uint16_t*>(feat);
+    h1b = featb + 32 * GL.k1;
+    yv = reinterpret_cast<float*>(h1b + 32 * GL.k2);
+    // the padding columns must read as zero (they meet zero weights)
+    for (int i = l; i < 32 * (GL.k1 + GL.k2); i += 64) featb[i] = 0;
+    wave_lds_sync();
   }
 
   const int wave_global = blockIdx.x * a.waves_per_block + wib;
@@ -415,10 +475,10 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       cid[0] = entry;
     }
     wave_lds_sync();
-    exact_dists<G, T4, 1>(a, qv, qlds, cid, 1, cd);
+    const float d_entry = exact_dists<G, T4, 1>(a, qv, qlds, cid, 1);
     int cur_buf = 0;
     if (l == 0) {
-      tD[0][0] = cd[0];
+      tD[0][0] = d_entry;
       tI[0][0] = entry;
     }
     wave_lds_sync();
@@ -506,14 +566,19 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
             log_base = (int64_t)shfl_u64((uint64_t)got, 0);
           }
           wave_lds_sync();
-          float base1 = 0.f;
+          float b1v[4] = {0.f, 0.f, 0.f, 0.f};
           if constexpr (MODE == FINGER_MODE_GATED) {
-            // shared part of the gate's first layer: b1 + W1[:, 0:r] w/|w|
-            if (l < a.gate_h) {
+            // shared part of the gate's first layer, b1 + W1[:, 0:r] w/|w|,
+            // one lane per hidden unit, then spread to the MFMA column layout
+            float base1 = 0.f;
+            if (l < GL.hp) {
               base1 = gb[l];
-              for (int i = 0; i < a.r; ++i) base1 += bf16_to_f(gw[i * a.gate_h + l]) * round_bf16(wv[i] * inv_w);
+              for (int i = 0; i < a.r; ++i) base1 += bf16_to_f(gw[i * GL.hp + l]) * round_bf16(wv[i] * inv_w);
             }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) b1v[nt] = __shfl(base1, 16 * nt + (l & 15), 64);
           }
+          bool skip_l = false;  // the decision for this lane's adjacency slot
           for (int p0 = 0; p0 < a.deg; p0 += a.spp) {
             const int slot = p0 + csub;
             const bool slot_new = slot < a.deg && ((newm >> slot) & 1ull);
@@ -551,41 +616,43 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
               }
             }
             if constexpr (MODE == FINGER_MODE_GATED) {
-              // stage this pass's edge features, then run the gate edge by edge
-              float* fu = feat + (int64_t)csub * (a.r + 4);
+              // this pass's new edges become the rows of a feature tile
+              // (compacted in slot order), which the gate evaluates on the
+              // matrix cores
+              const uint64_t hi = p0 + a.spp >= 64 ? ~0ull : ((1ull << (p0 + a.spp)) - 1ull);
+              const uint64_t pmask = newm & hi & ~((1ull << p0) - 1ull);
+              const int E = popc64(pmask);
+              const int row = slot_new ? popc64(pmask & ((1ull << slot) - 1ull)) : 0;
               if (slot_new) {
+                uint16_t* fr = featb + row * GL.k1;
                 for (int e = 0; e < kChunk; ++e) {
                   const int idx = ch * kChunk + e;
-                  if (idx < a.r) fu[idx] = round_bf16(code.at(e) * scl);
+                  if (idx < a.r) fr[idx] = bf16_bits(code.at(e) * scl);
                 }
                 if (ch == 0) {
-                  fu[a.r] = round_bf16(t_hat);
-                  fu[a.r + 1] = round_bf16(rq * inv_ub);
-                  fu[a.r + 2] = round_bf16(rh * inv_ub);
-                  fu[a.r + 3] = round_bf16(proj * inv_ub * inv_ub);
+                  fr[a.r] = bf16_bits(t_hat);
+                  fr[a.r + 1] = bf16_bits(rq * inv_ub);
+                  fr[a.r + 2] = bf16_bits(rh * inv_ub);
+                  fr[a.r + 3] = bf16_bits(proj * inv_ub * inv_ub);
                 }
               }
               wave_lds_sync();
-              float* hbuf = feat + (int64_t)a.spp * (a.r + 4);
-              const uint64_t pm = ballot(slot_new && ch == 0);
-              float mine = 0.f;
-              for (uint64_t mm = pm; mm; mm &= mm - 1ull) {
-                const int src = __ffsll((unsigned long long)mm) - 1;
-                const float* f = feat + (int64_t)(src / cpr) * (a.r + 4);
-                const float y = gate_edge(a, gw, gb, base1, f, f + a.r, hbuf);
-                if (l == src) mine = y;
-              }
-              t = mine + a.eps_gate;
+              gate_tiles(GL, gw, gb, b1v, featb, h1b, yv, E);
+              t = (slot_new ? yv[row] : 0.f) + a.eps_gate;
+              wave_lds_sync();
             } else {
               t = (t_hat - a.mu_hat) * a.dm_scale + a.mu + a.eps;
             }
             const float est = proj + rq2 + rh * rh - 2.f * rq * rh * t;
-            // skip iff the estimate exceeds ub (both squared)
-            if (slot_new && ch == 0) cflag[slot] = est > ub2 ? 1 : 0;
+            // skip iff the estimate exceeds ub (both squared); slot s of this
+            // pass is decided in lane (s - p0) cpr and handed to lane s
+            const int rel = l - p0;
+            const bool in_pass = rel >= 0 && rel < a.spp;
+            const int sk = __shfl(est > ub2 ? 1 : 0, (in_pass ? rel : 0) * cpr, 64);
+            if (in_pass) skip_l = sk != 0;
           }
-          wave_lds_sync();
           // back in adjacency lanes
-          const bool keep = isnew && cflag[l] == 0;
+          const bool keep = isnew && !skip_l;
           survm = ballot(keep);
           n_skip += S - popc64(survm);
           if (logging) {
@@ -613,64 +680,58 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       // 5. exact distances of the survivors
       // plain search keeps two passes of vectors in flight; after screening
       // few neighbours survive and one pass is enough
-      exact_dists<G, T4, MODE == FINGER_MODE_PLAIN ? 2 : 1>(a, qv, qlds, cid, S2, cd);
+      const float dmine = exact_dists<G, T4, MODE == FINGER_MODE_PLAIN ? 2 : 1>(a, qv, qlds, cid, S2);
 
-      // 6. admission: lanes 0..S2-1 hold (cd, cid)
+      // 6. admission: lanes 0..S2-1 hold (dmine, cid)
       uint64_t key = ~0ull;
       bool adm = false;
       bool was_skipped = false;
       const uint64_t worst_key = make_key(TD[tn - 1], (int)((uint32_t)TI[tn - 1] & ~kExpanded));
       if (l < S2) {
-        const float d = cd[l];
         if (logging) {
           was_skipped = cflag[l] != 0;
           const int64_t row = log_base + l;
           if (row < a.log_cap) {
-            a.log_y[2 * row] = d;
+            a.log_y[2 * row] = dmine;
             a.log_y[2 * row + 1] = ub2;
           }
         }
-        key = make_key(d, cid[l]);
+        key = make_key(dmine, cid[l]);
         adm = !was_skipped && (tn < ef_eff || key < worst_key);
       }
       n_exact += S2 - popc64(ballot(was_skipped));
       const uint64_t am = ballot(adm);
       const int NA = popc64(am);
       if (NA == 0) continue;
-      wave_lds_sync();
-      if (adm) ck[mask_rank(am)] = key;
-      wave_lds_sync();
-      // ranks: new key jn lands at (#new keys below it) + (#T keys below
-      // it); T entry i moves right by the number of new keys below it
+      // merge by ranks, with the new keys read across lanes: T entry i moves
+      // right by the number of new keys below it; a new key lands at (new
+      // keys below it) + (T keys below it)
       float* ND = tD[cur_buf ^ 1];
       int* NI = tI[cur_buf ^ 1];
-      for (int i = l; i < tn; i += 64) {
-        const int raw = TI[i];
-        const float d = TD[i];
-        const uint64_t tk = make_key(d, (int)((uint32_t)raw & ~kExpanded));
+      int my_pos = 0;
+      for (int b0 = 0; b0 < tn; b0 += 64) {
+        const int i = b0 + l;
+        const bool valid = i < tn;
+        const int raw = valid ? TI[i] : 0;
+        const float d = valid ? TD[i] : 0.f;
+        const uint64_t tk = valid ? make_key(d, (int)((uint32_t)raw & ~kExpanded)) : ~0ull;
         int shift = 0;
-        for (int jn = 0; jn < NA; ++jn) shift += ck[jn] < tk ? 1 : 0;  // broadcast reads
-        if (i + shift < ef_eff) {
+        for (uint64_t mm = am; mm; mm &= mm - 1ull) {
+          const int src = __ffsll((unsigned long long)mm) - 1;
+          const uint64_t kj = readlane_u64(key, src);
+          shift += kj < tk ? 1 : 0;
+          const int below = popc64(ballot(tk < kj));
+          if (l == src) my_pos += below;
+          if (b0 == 0) my_pos += kj < key ? 1 : 0;
+        }
+        if (valid && i + shift < ef_eff) {
           ND[i + shift] = d;
           NI[i + shift] = raw;
         }
       }
-      const uint64_t mykey = l < NA ? ck[l] : ~0ull;
-      int my_pos = 0;
-      for (int jn = 0; jn < NA; ++jn) {
-        const uint64_t kj = ck[jn];
-        my_pos += (kj < mykey) ? 1 : 0;
-        int below = 0;
-        for (int b0 = 0; b0 < tn; b0 += 64) {
-          const int i = b0 + l;
-          const bool lt = i < tn && make_key(TD[i], (int)((uint32_t)TI[i] & ~kExpanded)) < kj;
-          below += popc64(ballot(lt));
-        }
-        if (l == jn) my_pos += below;
-      }
-      if (l < NA && my_pos < ef_eff) {
-        ND[my_pos] = key_d2(mykey);
-        NI[my_pos] = key_id(mykey);
+      if (adm && my_pos < ef_eff) {
+        ND[my_pos] = key_d2(key);
+        NI[my_pos] = key_id(key);
       }
       tn = min(tn + NA, ef_eff);
       cur_buf ^= 1;
@@ -726,15 +787,21 @@ k_search_w4(KArgs a) {
   search_body<MODE, CODE, G, T4, PF>(a);
 }
 
-template <int MODE, int CODE, int G, int T4, bool PF>
-hipError_t launch_k(const KArgs& a, int blocks, int lds, hipStream_t s) {
-  auto fn = MODE == FINGER_MODE_FINGER ? k_search_w4<MODE, CODE, G, T4, PF>
-                                       : k_search<MODE, CODE, G, T4, PF>;
+template <typename F>
+hipError_t launch_fn(F fn, const KArgs& a, int blocks, int lds, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * a.waves_per_block), lds, s, a);
   return hipGetLastError();
+}
+
+template <int MODE, int CODE, int G, int T4, bool PF>
+hipError_t launch_k(const KArgs& a, int blocks, int lds, hipStream_t s) {
+  if constexpr (MODE == FINGER_MODE_FINGER)
+    return launch_fn(k_search_w4<MODE, CODE, G, T4, PF>, a, blocks, lds, s);
+  else
+    return launch_fn(k_search<MODE, CODE, G, T4, PF>, a, blocks, lds, s);
 }
 
 template <int MODE, int CODE, bool PF>
@@ -744,30 +811,28 @@ hipError_t launch_dims(const KArgs& a, int blocks, int lds, hipStream_t s) {
   return launch_k<MODE, CODE, 64, 8, PF>(a, blocks, lds, s);
 }
 
-template <int MODE>
-hipError_t launch_codes(const KArgs& a, int code, bool pf, int blocks, int lds, hipStream_t s) {
-  if (code == FINGER_CODE_BF16)
-    return pf ? launch_dims<MODE, FINGER_CODE_BF16, true>(a, blocks, lds, s)
-              : launch_dims<MODE, FINGER_CODE_BF16, false>(a, blocks, lds, s);
-  if (code == FINGER_CODE_FP8E4M3)
-    return pf ? launch_dims<MODE, FINGER_CODE_FP8E4M3, true>(a, blocks, lds, s)
-              : launch_dims<MODE, FINGER_CODE_FP8E4M3, false>(a, blocks, lds, s);
-  return pf ? launch_dims<MODE, FINGER_CODE_F32, true>(a, blocks, lds, s)
-            : launch_dims<MODE, FINGER_CODE_F32, false>(a, blocks, lds, s);
+template <int MODE, bool PF>
+hipError_t launch_codes_pf(const KArgs& a, int code, int blocks, int lds, hipStream_t s) {
+  if (code == FINGER_CODE_BF16) return launch_dims<MODE, FINGER_CODE_BF16, PF>(a, blocks, lds, s);
+  if (code == FINGER_CODE_FP8E4M3) return launch_dims<MODE, FINGER_CODE_FP8E4M3, PF>(a, blocks, lds, s);
+  return launch_dims<MODE, FINGER_CODE_F32, PF>(a, blocks, lds, s);
 }
 
-int gate_shared_bytes(int gate_h, int gate_in) {
-  if (gate_h <= 0) return 0;
-  const int nw = gate_h * gate_in + gate_h * gate_h + gate_h;
-  return ((2 * nw + 15) & ~15) + ((4 * (2 * gate_h + 1) + 15) & ~15);
+// PF_ALLOWED false: the mode always loads codes after the visited test
+template <int MODE, bool PF_ALLOWED = true>
+hipError_t launch_codes(const KArgs& a, int code, bool pf, int blocks, int lds, hipStream_t s) {
+  if constexpr (PF_ALLOWED)
+    if (pf) return launch_codes_pf<MODE, true>(a, code, blocks, lds, s);
+  return launch_codes_pf<MODE, false>(a, code, blocks, lds, s);
 }
 
 int wave_bytes(int ef_max, int vis_cap, int r, int m, int gate_in) {
   const int rpad = rpad_of(r);
-  int b = 16 * ef_max + 4 * vis_cap + 64 * 8 + 64 * 4 * 3 + 8 * rpad + (r > 0 ? 4 * m : 0);
+  int b = 16 * ef_max + 4 * vis_cap + 64 * 4 * 2 + 8 * rpad + (r > 0 ? 4 * m : 0);
   if (gate_in > 0) {
-    const int spp = 64 / (rpad / 16);  // at most this many slots per pass
-    b += 4 * (spp * (r + 4) + 64);
+    // edge features [32][k1] and hidden activations [32][k2] in bf16, outputs [32]
+    const GateLayout GL = gate_layout(r, 64);
+    b += 2 * 32 * (GL.k1 + GL.k2) + 4 * 32;
   }
   return (b + 15) & ~15;
 }
@@ -797,8 +862,8 @@ void fill_common(KArgs& a, const Tables& t) {
 
 }  // namespace
 
-int search_lds_bytes(int ef_max, int vis_cap, int r, int m, int gate_h, int gate_in) {
-  return gate_shared_bytes(gate_h, gate_in) + wave_bytes(ef_max, vis_cap, r, m, gate_in);
+int search_lds_bytes(int ef_max, int vis_cap, int r, int m, int gate_in) {
+  return wave_bytes(ef_max, vis_cap, r, m, gate_in);
 }
 
 bool search_prefetch_supported(const Tables& t) {
@@ -841,10 +906,9 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   a.gate_in = gated ? t.gate_in : 0;
   a.gate_h = gated ? t.gate_h : 0;
   a.eps_gate = (float)t.eps_gate;
-  // plain and FINGER: one query wave per workgroup keeps LDS allocation fine
-  // grained; the gated mode shares its weights among 4 waves
-  a.waves_per_block = gated ? 4 : 1;
-  a.lds_shared_bytes = gated ? gate_shared_bytes(a.gate_h, a.gate_in) : 0;
+  // one query wave per workgroup keeps LDS allocation fine grained
+  a.waves_per_block = 1;
+  a.lds_shared_bytes = 0;
   a.lds_wave_bytes = wave_bytes(L.ef_max, L.vis_cap, L.mode == FINGER_MODE_PLAIN ? 0 : t.r, t.m,
                                 gated ? a.gate_in : 0);
   const int lds = a.lds_shared_bytes + a.waves_per_block * a.lds_wave_bytes;
@@ -855,7 +919,7 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   if (L.mode == FINGER_MODE_FINGER && L.log_x != nullptr)
     return launch_codes<kModeLog>(a, t.code_type, pf, blocks, lds, s);
   if (L.mode == FINGER_MODE_FINGER) return launch_codes<FINGER_MODE_FINGER>(a, t.code_type, pf, blocks, lds, s);
-  return launch_codes<FINGER_MODE_GATED>(a, t.code_type, false, blocks, lds, s);
+  return launch_codes<FINGER_MODE_GATED, false>(a, t.code_type, false, blocks, lds, s);
 }
 
 // ------------------------------------------------- estimate test kernel
