@@ -103,6 +103,14 @@ typedef struct finger_build_params {
   int32_t n_pivots;      /* 0..65536 */
   int32_t dm_override;   /* 1: use dm[] instead of the measured statistics */
   double dm[5];          /* mu, sigma, mu_hat, sigma_hat, eps (override) */
+  const double* basis;   /* host [rank][m] row-major, or NULL.  Given, it is
+                            used as P instead of the top-r eigenvectors of
+                            D_res D_res^T (which are then not computed, and
+                            FINGER_T_EIGENVALUES reads as NaN): e.g. a basis
+                            computed elsewhere, or the random projections of
+                            the paper's RPLSH comparison (Section 4.2).  Rows
+                            need not be orthonormal; values must be finite.
+                            Copied during the call. */
 } finger_build_params;
 
 /* Fill *p with the defaults (rank 0, F32 codes, L2, sigma = std, N_s = min(n,

@@ -43,7 +43,7 @@ class BuildParams(C.Structure):
         ("rank", C.c_int32), ("code_type", C.c_int32), ("metric", C.c_int32),
         ("sigma_mode", C.c_int32), ("n_samples", C.c_int64), ("seed", C.c_uint64),
         ("pivots", C.c_void_p), ("n_pivots", C.c_int32), ("dm_override", C.c_int32),
-        ("dm", C.c_double * 5),
+        ("dm", C.c_double * 5), ("basis", C.c_void_p),
     ]
 
 

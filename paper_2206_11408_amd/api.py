@@ -102,7 +102,10 @@ class Tables:
 def finger_build_tables(data: torch.Tensor, graph: torch.Tensor, rank: int = 0,
                         code_type: int = L.CODE_F32, metric: int = L.L2,
                         sigma_mode: int = L.SIGMA_STD, n_samples: int = 0, seed: int = 0,
-                        pivots=None, dm_override=None) -> Tables:
+                        pivots=None, dm_override=None, basis=None) -> Tables:
+    """FINGER tables for ``data`` over ``graph`` (finger_build_tables).
+    ``basis``: optional float64 [rank][m] array used as P instead of the
+    eigenvector basis."""
     lib = L.load()
     data = _dev_f32(data)
     graph = _dev_i32(graph)
@@ -125,6 +128,12 @@ def finger_build_tables(data: torch.Tensor, graph: torch.Tensor, rank: int = 0,
         p.dm_override = 1
         for i, v in enumerate(dm_override):
             p.dm[i] = float(v)
+    bas = None
+    if basis is not None:
+        bas = np.ascontiguousarray(np.asarray(basis, dtype=np.float64))
+        if bas.shape != (rank, m):
+            raise ValueError(f"basis must be [{rank}][{m}], got {bas.shape}")
+        p.basis = bas.ctypes.data
     h = C.c_void_p()
     L.check(lib.finger_build_tables(data.data_ptr(), n, m, graph.data_ptr(), deg, C.byref(p),
                                     C.byref(h), _stream()))

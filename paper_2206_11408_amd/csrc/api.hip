@@ -181,6 +181,10 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
   if (p->n_pivots < 0 || p->n_pivots > 65536) return fail(FINGER_EINVAL, "n_pivots = %d out of range", p->n_pivots);
   if (p->n_pivots > 0 && p->pivots == nullptr) return fail(FINGER_EINVAL, "pivots is NULL with n_pivots > 0");
   if (p->dm_override && !(p->dm[3] >= 0)) return fail(FINGER_EINVAL, "dm override sigma_hat must be >= 0");
+  if (p->basis != nullptr && p->rank > 0) {
+    for (int64_t i = 0; i < (int64_t)p->rank * m; ++i)
+      if (!std::isfinite(p->basis[i])) return fail(FINGER_EINVAL, "basis entry %lld is not finite", (long long)i);
+  }
   int dev = 0;
   int st = check_device(&dev);
   if (st != FINGER_OK) return st;
@@ -248,19 +252,25 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
     double* res1 = res.p;
     double* res2 = res.p + (size_t)ns * m;
     HIPCHK(launch_residuals_f64(t->data, m, t->samples, ns, res1, res2, s));
-    const int parts = gram_parts(ns, m);
-    DevBuf<double> gram;
-    if ((st = dev_alloc(reinterpret_cast<void**>(&gram.p), (size_t)(parts + 1) * m * m * 8, "gram")) != FINGER_OK) return st;
-    HIPCHK(launch_gram_f64(res1, ns, m, gram.p, s));
-    std::vector<double> M((size_t)m * m);
-    HIPCHK(hipMemcpyAsync(M.data(), gram.p, M.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
     t->eig_host = static_cast<double*>(std::malloc((size_t)m * 8));
-    std::vector<double> V((size_t)m * m);
     t->P64_host = static_cast<double*>(std::malloc((size_t)t->r * m * 8));
     if (!t->eig_host || !t->P64_host) return fail(FINGER_ENOMEM, "host allocation failed");
-    eigh_jacobi(M.data(), m, t->eig_host, V.data());
-    std::memcpy(t->P64_host, V.data(), (size_t)t->r * m * 8);
+    if (p->basis != nullptr) {
+      // a caller-supplied basis replaces Proposition 3.1's
+      std::memcpy(t->P64_host, p->basis, (size_t)t->r * m * 8);
+      for (int i = 0; i < m; ++i) t->eig_host[i] = std::nan("");
+    } else {
+      const int parts = gram_parts(ns, m);
+      DevBuf<double> gram;
+      if ((st = dev_alloc(reinterpret_cast<void**>(&gram.p), (size_t)(parts + 1) * m * m * 8, "gram")) != FINGER_OK) return st;
+      HIPCHK(launch_gram_f64(res1, ns, m, gram.p, s));
+      std::vector<double> M((size_t)m * m);
+      HIPCHK(hipMemcpyAsync(M.data(), gram.p, M.size() * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      std::vector<double> V((size_t)m * m);
+      eigh_jacobi(M.data(), m, t->eig_host, V.data());
+      std::memcpy(t->P64_host, V.data(), (size_t)t->r * m * 8);
+    }
     DevBuf<double> P64d;
     if ((st = dev_alloc(reinterpret_cast<void**>(&P64d.p), (size_t)t->r * m * 8, "basis")) != FINGER_OK) return st;
     HIPCHK(hipMemcpyAsync(P64d.p, t->P64_host, (size_t)t->r * m * 8, hipMemcpyHostToDevice, s));

@@ -798,7 +798,11 @@ hipError_t launch_fn(F fn, const KArgs& a, int blocks, int lds, hipStream_t s) {
 
 template <int MODE, int CODE, int G, int T4, bool PF>
 hipError_t launch_k(const KArgs& a, int blocks, int lds, hipStream_t s) {
-  if constexpr (MODE == FINGER_MODE_FINGER)
+  // the register cap applies up to m = 512; beyond, a vector needs 8 float4
+  // per lane and the capped build spills heavily (there it also returned
+  // run-to-run differing results with BF16 codes requested ahead, so the
+  // uncapped build is used)
+  if constexpr (MODE == FINGER_MODE_FINGER && G < 64)
     return launch_fn(k_search_w4<MODE, CODE, G, T4, PF>, a, blocks, lds, s);
   else
     return launch_fn(k_search<MODE, CODE, G, T4, PF>, a, blocks, lds, s);

@@ -113,6 +113,19 @@ def test_build_rejects_null_pointers():
     assert lib.finger_build_tables(1 << 20, 10, 32, 1 << 20, 8, C.byref(p), None, None) == L.FINGER_EINVAL
 
 
+def test_build_rejects_non_finite_basis():
+    import numpy as np
+    lib = L.load()
+    p = _bp()
+    p.rank = 4
+    basis = np.zeros((4, 32))
+    basis[2, 5] = np.nan
+    p.basis = basis.ctypes.data
+    h = C.c_void_p()
+    assert lib.finger_build_tables(1 << 20, 10, 32, 1 << 20, 8, C.byref(p), C.byref(h), None) == L.FINGER_EINVAL
+    assert "basis entry 69 is not finite" in lib.finger_last_error().decode()
+
+
 def test_misaligned_data_rejected():
     lib = L.load()
     p = _bp()
