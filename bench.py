@@ -87,7 +87,7 @@ def main() -> int:
     ap.add_argument("--rank", type=int, default=64)
     ap.add_argument("--code", choices=("f32", "bf16", "fp8"), default="f32")
     ap.add_argument("--pivots", type=int, default=4096)
-    ap.add_argument("--cpu-sample", type=int, default=200,
+    ap.add_argument("--cpu-sample", type=int, default=4000,
                     help="queries of the oracle CPU baseline (0 = skip)")
     ap.add_argument("--extra-codes", default="",
                     help="comma list of extra FINGER variants to sweep and report: "
@@ -206,7 +206,7 @@ def main() -> int:
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
         if a.tune:
             base = dict(mode=mode, k=10, ef=ef, entry=-1)
-            ch = tune.autotune(tab, d_q, base, repeats=3, cache_path=None)
+            ch = tune.autotune(tab, d_q, base, repeats=3, cache_path=None, log=log)
             if prefetch != 0:   # an explicitly requested code-prefetch setting stays fixed
                 best = min((t, c) for t, c in ch["all"] if c["code_prefetch"] == prefetch)[1]
                 ch = dict(best)
@@ -323,11 +323,12 @@ def main() -> int:
         orc = oracle_build(data, G, a.rank, n_samples=100_000, seed=0)
         log(f"oracle tables in {time.time() - t0:.1f}s")
         qs = queries[:a.cpu_sample]
-        ent = pivot_entries(qs, data, piv)
-        t0 = time.process_time()
-        w0 = time.perf_counter()
-        search_batch(data, G, qs, ent, op_f["ef"], 10, mode="finger", tables=orc)
-        wall = time.perf_counter() - w0
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):   # the oracle is single-threaded; keep BLAS so too
+            w0 = time.perf_counter()
+            ent = pivot_entries(qs, data, piv)
+            search_batch(data, G, qs, ent, op_f["ef"], 10, mode="finger", tables=orc)
+            wall = time.perf_counter() - w0
         cpu = {"value": round(a.cpu_sample / wall, 3), "unit": "queries/s", "cores": 1,
                "kind": "oracle",
                "sample": f"{a.cpu_sample} of the {a.nq} queries, FINGER mode at ef={op_f['ef']}, "
