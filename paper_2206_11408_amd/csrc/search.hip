@@ -381,7 +381,9 @@ template <int MODE, int CODE, int G, int T4, bool PREFETCH>
 __device__ __forceinline__ void search_body(const KArgs& a) {
   extern __shared__ __align__(16) char smem[];
   const int l = lane_id();
-  const int wib = threadIdx.x / 64;
+  // wave-uniform values are kept in scalar registers (readfirstlane), so the
+  // address arithmetic that depends only on them runs on the scalar unit
+  const int wib = uniform_i(threadIdx.x / 64);
   char* base = smem + a.lds_shared_bytes + wib * a.lds_wave_bytes;
   float* tD[2];
   int* tI[2];
@@ -500,9 +502,9 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
         }
       }
       if (j < 0) break;
-      const int cur = TI[j];
-      const float dcur = TD[j];
-      const float ub2 = TD[tn - 1];
+      const int cur = uniform_i(TI[j]);
+      const float dcur = uniform_f(TD[j]);
+      const float ub2 = uniform_f(TD[tn - 1]);
       wave_lds_sync();
       if (l == 0) TI[j] = (int)((uint32_t)cur | kExpanded);
       ++n_exp;
@@ -686,7 +688,8 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       uint64_t key = ~0ull;
       bool adm = false;
       bool was_skipped = false;
-      const uint64_t worst_key = make_key(TD[tn - 1], (int)((uint32_t)TI[tn - 1] & ~kExpanded));
+      const uint64_t worst_key = make_key(uniform_f(TD[tn - 1]),
+                                          uniform_i((int)((uint32_t)TI[tn - 1] & ~kExpanded)));
       if (l < S2) {
         if (logging) {
           was_skipped = cflag[l] != 0;
