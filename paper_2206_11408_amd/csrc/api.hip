@@ -100,7 +100,7 @@ int next_pow2(int x) {
 void free_tables(Tables* t) {
   if (t == nullptr) return;
   void* dev_ptrs[] = {t->data_owned, t->P, t->cc, t->pc, t->alpha, t->rho, t->codes, t->scale,
-                      t->piv_ids, t->qprep_B, t->qprep_Bnorm, t->piv_b16, t->samples, t->xy, t->gate_w,
+                      t->piv_ids, t->qprep_B, t->qprep_Bnorm, t->piv_b16, t->piv_norm, t->samples, t->xy, t->gate_w,
                       t->gate_b};
   for (void* p : dev_ptrs)
     if (p) (void)hipFree(p);
@@ -350,6 +350,13 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
       HIPCHK(launch_pack_pivots(t->qprep_B + (size_t)rcols * m, t->npiv, m, t->piv_b16, s));
     }
     HIPCHK(launch_row_norms(t->qprep_B, cols, m, t->qprep_Bnorm, s));
+    if (t->npiv > 0) {
+      const size_t np = (size_t)pivot_pad_rows(t->npiv);
+      if ((st = dev_alloc(reinterpret_cast<void**>(&t->piv_norm), np * 4, "pivot norms")) != FINGER_OK) return st;
+      HIPCHK(hipMemsetAsync(t->piv_norm, 0, np * 4, s));
+      HIPCHK(hipMemcpyAsync(t->piv_norm, t->qprep_Bnorm + rcols, (size_t)t->npiv * 4,
+                            hipMemcpyDeviceToDevice, s));
+    }
   }
   HIPCHK(hipStreamSynchronize(s));
   guard.t = nullptr;

@@ -128,19 +128,39 @@ __global__ void __launch_bounds__(256) k_qprep(const float* Q, int64_t nq, const
 // (both exact for integers up to 256); products accumulate in float32.  One
 // wave owns 16 queries and one of kPivSplit pivot ranges, walks that range in
 // 16-pivot tiles, and keeps in every lane the lowest (score, pivot) of the
-// columns that land on it, so each query ends with kPivCand candidates (one
-// per lane stripe and range) without any cross-lane work in the loop.
+// columns that land on it (no cross-lane work in the loop); at the end each
+// query row keeps the best kPivKeep of its 16 stripe minima, so a query has
+// kPivCand = kPivSplit kPivKeep candidates.  Many short ranges give enough
+// waves to hide the latency of the pivot tiles, which come from L2.
 //
 // Stage 2 (k_qfinish, one wave per query) sorts the candidates by score and
 // re-ranks the best kPivRerank by exact float32 direct differences; the
 // nearest (ties to the smaller pivot index) becomes the entry.
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
-constexpr int kPivSplit = 4;              // pivot ranges per 16-query tile
-constexpr int kPivCand = 16 * kPivSplit;  // candidates per query (= 64, one per lane)
+constexpr int kPivSplit = 16;                    // pivot ranges per 16-query tile
+constexpr int kPivKeep = 4;                      // candidates kept per query and range
+constexpr int kPivCand = kPivKeep * kPivSplit;   // candidates per query (= 64, one per lane)
 constexpr int kPivRerank = 16;            // candidates re-ranked exactly
 constexpr int kPivKs = 8;                 // 32-wide k-steps of a query held in registers
+constexpr int kPivTiles = 2;              // 16-row query tiles per wave
+constexpr int kPivRows = 16 * kPivTiles;  // queries per wave
 
 static_assert(kPivCand == 64, "k_qfinish sorts one candidate per lane");
+
+// ascending sort of one key per lane within each aligned group of 16 lanes
+__device__ __forceinline__ uint64_t sort16(uint64_t v) {
+  const int g = lane_id() & 15;
+#pragma unroll
+  for (int k = 2; k <= 16; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t o = shfl_xor_u64(v, j);
+      const bool take_min = ((g & j) == 0) == ((g & k) == 0 || k == 16);
+      v = take_min ? (v < o ? v : o) : (v < o ? o : v);
+    }
+  }
+  return v;
+}
 
 // float -> unsigned with the same order (negative scores included)
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
@@ -170,11 +190,11 @@ __device__ __forceinline__ b8v load_query_frag(const float* __restrict__ Q, int6
   return r;
 }
 
-// Fold one 16x16 score tile into the per-lane running minima.
-__device__ __forceinline__ void fold_tile(const f4v& acc, int col, int npiv,
-                                          const float* __restrict__ pnorm, uint64_t best[4]) {
+// Fold one 16x16 score tile into the per-lane running minima (pn = |p|^2 of
+// this lane's column, loaded with the tile).
+__device__ __forceinline__ void fold_tile(const f4v& acc, int col, int npiv, float pn,
+                                          uint64_t best[4]) {
   if (col >= npiv) return;
-  const float pn = pnorm[col];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const uint64_t k = ((uint64_t)ordered_bits(pn - 2.f * acc[v]) << 32) | (uint32_t)col;
@@ -182,8 +202,9 @@ __device__ __forceinline__ void fold_tile(const f4v& acc, int col, int npiv,
   }
 }
 
-// grid: ceil(nq / 16) * kPivSplit waves, 4 per block; PB [npad][kpad] bf16,
-// npad = kPivSplit * range, rows >= npiv zero; cand [nq][kPivCand].
+// grid: ceil(nq / kPivRows) * kPivSplit waves, 4 per block; PB [npad][kpad] bf16
+// and pnorm [npad], npad = kPivSplit * range with range a multiple of 32,
+// rows >= npiv zero; cand [nq][kPivCand].
 // KS: 32-wide k-steps (kpad = 32 KS) when the query fits in registers
 // (KS <= kPivKs); KS = 0 is the general path that streams the query in
 // chunks of kPivKs steps.  The pivot tile of the next iteration is loaded
@@ -194,69 +215,95 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
                                                       const float* __restrict__ pnorm, int npiv,
                                                       int kpad, int range,
                                                       uint64_t* __restrict__ cand) {
-  const int64_t wid = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  const int64_t q0 = (wid / kPivSplit) * 16;
+  // one wave: kPivRows queries (kPivTiles 16-row MFMA tiles share every pivot
+  // tile it loads) x one pivot range
+  constexpr int NT = kPivTiles;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + uniform_i(threadIdx.x / 64);
+  const int64_t q0 = (wid / kPivSplit) * kPivRows;
   const int split = (int)(wid % kPivSplit);
   if (q0 >= nq) return;  // whole waves only
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lk = 8 * (l >> 4);
   const int c_beg = split * range;
-  uint64_t best[4] = {~0ull, ~0ull, ~0ull, ~0ull};
-  if constexpr (KS > 0) {
-    b8v a[KS];
+  uint64_t best[NT][4];
 #pragma unroll
-    for (int i = 0; i < KS; ++i) a[i] = load_query_frag(Q, nq, m, q0 + lr, 32 * i + lk);
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) best[u][v] = ~0ull;
+  if constexpr (KS > 0) {
+    b8v a[NT][KS];
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int i = 0; i < KS; ++i) a[u][i] = load_query_frag(Q, nq, m, q0 + 16 * u + lr, 32 * i + lk);
+    // range is a multiple of 32 and PB / pnorm hold every padded row, so the
+    // loop loads unconditionally: bx (tile t) is multiplied while by (tile
+    // t + 16) is in flight and the other way round, and the wait counts stay
+    // exact (no loads under branches)
     const __bf16* base = PB + (int64_t)(c_beg + lr) * kpad + lk;
+    const float* pbase = pnorm + c_beg + lr;
     b8v bx[KS], by[KS];
 #pragma unroll
     for (int i = 0; i < KS; ++i) bx[i] = *reinterpret_cast<const b8v*>(base + 32 * i);
-    // range is a multiple of 16: tiles t = 0, 16, ...; bx holds tile t, by tile t + 16
+    float px = pbase[0], py;
     for (int t = 0; t < range; t += 32) {
-      const bool has_y = t + 16 < range;
-      if (has_y) {
 #pragma unroll
-        for (int i = 0; i < KS; ++i)
-          by[i] = *reinterpret_cast<const b8v*>(base + (int64_t)(t + 16) * kpad + 32 * i);
-      }
-      f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < KS; ++i)
+        by[i] = *reinterpret_cast<const b8v*>(base + (int64_t)(t + 16) * kpad + 32 * i);
+      py = pbase[t + 16];
+      f4v c[NT];
 #pragma unroll
-      for (int i = 0; i < KS; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bx[i], acc, 0, 0, 0);
-      fold_tile(acc, c_beg + t + lr, npiv, pnorm, best);
-      if (!has_y) break;
-      if (t + 32 < range) {
+      for (int u = 0; u < NT; ++u) c[u] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int i = 0; i < KS; ++i)
-          bx[i] = *reinterpret_cast<const b8v*>(base + (int64_t)(t + 32) * kpad + 32 * i);
-      }
-      acc = f4v{0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < KS; ++i)
 #pragma unroll
-      for (int i = 0; i < KS; ++i) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], by[i], acc, 0, 0, 0);
-      fold_tile(acc, c_beg + t + 16 + lr, npiv, pnorm, best);
+        for (int u = 0; u < NT; ++u) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], bx[i], c[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < NT; ++u) fold_tile(c[u], c_beg + t + lr, npiv, px, best[u]);
+      // next tile pair (the last iteration reloads its own first tile, unused)
+      const int tn = t + 32 < range ? t + 32 : t;
+#pragma unroll
+      for (int i = 0; i < KS; ++i)
+        bx[i] = *reinterpret_cast<const b8v*>(base + (int64_t)tn * kpad + 32 * i);
+      px = pbase[tn];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) c[u] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int i = 0; i < KS; ++i)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], by[i], c[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < NT; ++u) fold_tile(c[u], c_beg + t + 16 + lr, npiv, py, best[u]);
     }
   } else {
+    // long vectors: the query fragments are re-read (cached) per pivot tile
     const int ksteps = kpad / 32;
-    b8v a[kPivKs], b[kPivKs];
     for (int t = 0; t < range; t += 16) {
-      f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
-      for (int c = 0; c < ksteps; c += kPivKs) {
+      f4v c[NT];
 #pragma unroll
-        for (int i = 0; i < kPivKs; ++i) {
-          if (c + i < ksteps) {
-            a[i] = load_query_frag(Q, nq, m, q0 + lr, 32 * (c + i) + lk);
-            b[i] = *reinterpret_cast<const b8v*>(PB + (int64_t)(c_beg + t + lr) * kpad + 32 * (c + i) + lk);
-          }
-        }
+      for (int u = 0; u < NT; ++u) c[u] = f4v{0.f, 0.f, 0.f, 0.f};
+      for (int ks = 0; ks < ksteps; ++ks) {
+        const b8v b = *reinterpret_cast<const b8v*>(PB + (int64_t)(c_beg + t + lr) * kpad + 32 * ks + lk);
 #pragma unroll
-        for (int i = 0; i < kPivKs; ++i)
-          if (c + i < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[i], acc, 0, 0, 0);
+        for (int u = 0; u < NT; ++u)
+          c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              load_query_frag(Q, nq, m, q0 + 16 * u + lr, 32 * ks + lk), b, c[u], 0, 0, 0);
       }
-      fold_tile(acc, c_beg + t + lr, npiv, pnorm, best);
+      const int col = c_beg + t + lr;
+      const float pn = pnorm[col];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) fold_tile(c[u], col, npiv, pn, best[u]);
     }
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int64_t row = q0 + 4 * (l >> 4) + v;
-    if (row < nq) cand[row * kPivCand + split * 16 + lr] = best[v];
+  for (int u = 0; u < NT; ++u) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // row 4(l/16)+v of tile u: its 16 stripe minima, ascending
+      const uint64_t srt = sort16(best[u][v]);
+      const int64_t row = q0 + 16 * u + 4 * (l >> 4) + v;
+      if (lr < kPivKeep && row < nq) cand[row * kPivCand + split * kPivKeep + lr] = srt;
+    }
   }
 }
 
@@ -266,7 +313,7 @@ __global__ void k_qfinish(const float* __restrict__ Q, int64_t nq, int m,
                           const float* __restrict__ PF, const int32_t* __restrict__ piv_ids,
                           int npiv, const uint64_t* __restrict__ cand, float* __restrict__ qq,
                           int32_t* __restrict__ entries) {
-  const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + uniform_i(threadIdx.x / 64);
   if (q >= nq) return;
   const int l = threadIdx.x & 63;
   const float* qv = Q + q * m;
@@ -324,7 +371,7 @@ size_t query_prep_scratch_bytes(const Tables& t, int64_t nq) {
   return t.npiv > 0 ? (size_t)nq * kPivCand * sizeof(uint64_t) : 0;
 }
 
-int pivot_pad_rows(int npiv) { return (npiv + 16 * kPivSplit - 1) / (16 * kPivSplit) * (16 * kPivSplit); }
+int pivot_pad_rows(int npiv) { return (npiv + 32 * kPivSplit - 1) / (32 * kPivSplit) * (32 * kPivSplit); }
 int pivot_kpad(int m) { return (m + 31) / 32 * 32; }
 
 hipError_t launch_pack_pivots(const float* src, int npiv, int m, __bf16* dst, hipStream_t s) {
@@ -351,11 +398,11 @@ hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float*
     if (e != hipSuccess) return e;
   }
   if (piv) {
-    const int64_t waves = (nq + 15) / 16 * kPivSplit;
+    const int64_t waves = (nq + kPivRows - 1) / kPivRows * kPivSplit;
     const int range = pivot_pad_rows(t.npiv) / kPivSplit;
     const int kpad = pivot_kpad(t.m);
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
-    const float* pn = t.qprep_Bnorm + rcols;
+    const float* pn = t.piv_norm;
     switch (kpad / 32) {
       case 1: hipLaunchKernelGGL(k_pivot_scores<1>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
       case 2: hipLaunchKernelGGL(k_pivot_scores<2>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;

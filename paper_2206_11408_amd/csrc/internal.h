@@ -68,6 +68,7 @@ struct Tables {
   int32_t* piv_ids = nullptr;      // [npiv]
   float* qprep_B = nullptr;        // [(r + npiv) rounded up to 64][m]
   __bf16* piv_b16 = nullptr;       // [pivot_pad_rows(npiv)][pivot_kpad(m)] pivots in bf16, zero padded
+  float* piv_norm = nullptr;       // [pivot_pad_rows(npiv)] |pivot|^2 (fp32), zero padded
   float* qprep_Bnorm = nullptr;    // [(r + npiv) rounded up to 64]  (|row|^2)
   int32_t qprep_cols = 0;          // r + npiv rounded up to 64
   // distribution matching constants

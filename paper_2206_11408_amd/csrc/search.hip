@@ -543,6 +543,31 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           // 4. screening
           n_scr += S;
           ++n_prep;
+          // code requests for the new slots, issued together so that the
+          // screen costs one round trip when fp32 codes take two passes
+          // (r = 64: 16 slots per pass): pass 1 (slot csub, unless requested
+          // with the adjacency row) and pass 2 (slot spp + csub, with its
+          // alpha and rho).  BF16/FP8 codes of r <= 64 fit one pass.
+          constexpr bool kPreload2 = CODE == FINGER_CODE_F32;
+          if constexpr (!PREFETCH) {
+            if (csub < a.deg && ((newm >> csub) & 1ull))
+              code.load(a.codes, ((int64_t)cur * a.deg + csub) * a.rpad + ch * kChunk);
+            else
+              code.zero();
+          }
+          Chunk<CODE> code2;
+          float al2 = 0.f, rh2 = 0.f;
+          if (kPreload2 && a.spp < a.deg) {
+            const int s2 = a.spp + csub;
+            if (s2 < a.deg) {
+              al2 = a.alpha[(int64_t)cur * a.deg + s2];
+              rh2 = a.rho[(int64_t)cur * a.deg + s2];
+            }
+            if (s2 < a.deg && ((newm >> s2) & 1ull))
+              code2.load(a.codes, ((int64_t)cur * a.deg + s2) * a.rpad + ch * kChunk);
+            else
+              code2.zero();
+          }
           // query side (Section 3.2 and Supplementary G): q.c from the exact
           // d2 of the centre, alpha_q, |q_res|^2, w = Pq - alpha_q P c
           const float qc = 0.5f * (qq + ccv - dcur);
@@ -584,11 +609,15 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           for (int p0 = 0; p0 < a.deg; p0 += a.spp) {
             const int slot = p0 + csub;
             const bool slot_new = slot < a.deg && ((newm >> slot) & 1ull);
-            if (p0 > 0 && slot < a.deg) {
-              al = a.alpha[(int64_t)cur * a.deg + slot];
-              rh = a.rho[(int64_t)cur * a.deg + slot];
-            }
-            if (!PREFETCH || p0 > 0) {
+            if (kPreload2 && p0 == a.spp) {
+              al = al2;
+              rh = rh2;
+              code = code2;
+            } else if (p0 > 0) {
+              if (slot < a.deg) {
+                al = a.alpha[(int64_t)cur * a.deg + slot];
+                rh = a.rho[(int64_t)cur * a.deg + slot];
+              }
               if (slot_new) code.load(a.codes, ((int64_t)cur * a.deg + slot) * a.rpad + ch * kChunk);
               else code.zero();
             }
