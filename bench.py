@@ -98,6 +98,9 @@ def main() -> int:
     ap.add_argument("--gate", type=int, default=0,
                     help="train the learned gate on this many extra queries (0 = skip) and "
                          "report the gated search")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also run the ablation variants (low-rank only, random projections with "
+                         "and without distribution matching) and the rank rule")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="time the default launch geometry instead of the autotuned one")
     ap.add_argument("--copy-probe", action="store_true",
@@ -314,6 +317,38 @@ def main() -> int:
                      speedup_vs_finger=round(tg["qps"] / tf["qps"], 4), exact=round(tg["exact"], 1),
                      train_rows=info["rows"], eps_gate=round(info["eps_gate"], 5))
 
+    ablation_out = None
+    if a.ablation:
+        from paper_2206_11408_amd import ablation
+        from workloads import gaussian_projection
+        proj = gaussian_projection(a.rank, spec.m, 7)
+        ablation_out = {}
+        nq_err = min(2000, a.nq)
+        for v in ablation.VARIANTS:
+            tab = tabF if v == "finger" else ablation.variant_tables(
+                d_data, d_G, a.rank, v, projection=proj, pivots=piv, seed=0)
+            sw, op = sweep(tab, L.MODE_FINGER)
+            err = ablation.approximation_error(tab, d_q[:nq_err], op["ef"])
+            curve = [dict(ef=r_["ef"], recall=round(r_["recall"], 4),
+                          effective_calls=round(r_["exact"] + r_["screened"] * a.rank / spec.m, 1),
+                          exact=round(r_["exact"], 1), ms=round(r_["ms"], 3)) for r_ in sw]
+            ablation_out[v] = dict(ef=op["ef"], recall=round(op["recall"], 4), qps=round(op["qps"], 1),
+                                   effective_calls=round(op["exact"] + op["screened"] * a.rank / spec.m, 1),
+                                   approx_error_median=round(err["median"], 5),
+                                   approx_error_p90=round(err["p90"], 5), curve=curve)
+            log(f"ablation {v}: {ablation_out[v] | {'curve': len(curve)}}")
+            if v != "finger":
+                tab.close()
+        r_sel, t_sel, hist = ablation.select_rank(d_data, d_G, target=0.7, pivots=piv, seed=0)
+        sw, op = sweep(t_sel, L.MODE_FINGER)
+        ablation_out["rank_rule"] = dict(rank=r_sel, corr_history=[(r_, round(c_, 4)) for r_, c_ in hist],
+                                         ef=op["ef"], recall=round(op["recall"], 4),
+                                         qps=round(op["qps"], 1),
+                                         effective_calls=round(op["exact"] + op["screened"] * r_sel / spec.m, 1))
+        ablation_out["plain"] = dict(ef=op_p["ef"], effective_calls=round(tp["exact"], 1))
+        log(f"rank rule: {ablation_out['rank_rule']}")
+        t_sel.close()
+
     # ------------------------------------------------------ CPU baseline
     cpu = None
     if a.cpu_sample > 0:
@@ -369,6 +404,8 @@ def main() -> int:
         line["extra_codes"] = extra
     if gated:
         line["gated"] = gated
+    if ablation_out:
+        line["ablation"] = ablation_out
     print(json.dumps(line), flush=True)
     return 0
 

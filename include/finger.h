@@ -165,6 +165,9 @@ typedef struct finger_tables_info {
   double eps_gate;          /* learned-gate correction (0 if no gate) */
   int32_t gate_attached;
   int64_t edge_table_bytes; /* bytes of alpha, rho and u over all slots */
+  double corr_xy;           /* Pearson correlation of the sampled X (true residual
+                               cosines) and Y (low-rank ones): Supplementary E's
+                               rank rule grows r until it reaches 0.7 */
 } finger_tables_info;
 
 FINGER_API int finger_tables_info_get(const finger_tables* t, finger_tables_info* info /* host */);

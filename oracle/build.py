@@ -103,18 +103,50 @@ def dm_stats(X: np.ndarray, Y: np.ndarray, sigma_mode: str = "std"):
 
 def build(data: np.ndarray, graph: np.ndarray, rank: int,
           n_samples: int = 100_000, seed: int = 0,
-          sigma_mode: str = "std") -> dict:
+          sigma_mode: str = "std", basis: np.ndarray | None = None) -> dict:
     """Algorithm 2.  Returns P (r x m, float64), the five distribution
-    parameters and the intermediate samples for inspection."""
+    parameters, the Pearson correlation of X and Y (Supplementary E) and
+    the intermediate samples for inspection.
+
+    ``basis`` (r x m) replaces Proposition 3.1's P, e.g. with the random
+    Gaussian projections of RPLSH that the ablation study compares against
+    (Section 4.4); the distribution-matching statistics are then taken with
+    that P."""
     c, d, dp, idx = sample_pairs(graph, n_samples, seed)
     Dres, Dres2 = residual_pairs(data, c, d, dp)
-    P, S = basis_from_residuals(Dres, rank)
+    if basis is None:
+        P, S = basis_from_residuals(Dres, rank)
+    else:
+        P, S = np.asarray(basis, dtype=np.float64), None
+        assert P.shape == (rank, data.shape[1])
     X = cosine_rows(Dres, Dres2)
     Y = cosine_rows(Dres @ P.T, Dres2 @ P.T)
     out = dm_stats(X, Y, sigma_mode)
-    out.update(P=P, singular_values=S, X=X, Y=Y,
+    out.update(P=P, singular_values=S, X=X, Y=Y, corr=pearson(X, Y),
                samples=(c, d, dp, idx), rank=rank)
     return out
+
+
+def pearson(X: np.ndarray, Y: np.ndarray) -> float:
+    """Correlation coefficient of two samples (0 if either is constant)."""
+    dx, dy = X - X.mean(), Y - Y.mean()
+    den = np.sqrt((dx * dx).sum() * (dy * dy).sum())
+    return float((dx * dy).sum() / den) if den > 0 else 0.0
+
+
+def select_rank(data: np.ndarray, graph: np.ndarray, target: float = 0.7, start: int = 8,
+                step: int = 8, max_rank: int | None = None, **build_kw) -> tuple[int, dict]:
+    """Supplementary E's rule of thumb: start at r = 8 and grow r by 8 until
+    the correlation of X and Y from Algorithm 2 reaches 0.7 (or r reaches
+    min(m, max_rank)).  Returns (r, tables of that r)."""
+    m = data.shape[1]
+    top = m if max_rank is None else min(m, max_rank)
+    r = min(start, top)
+    while True:
+        t = build(data, graph, r, **build_kw)
+        if t["corr"] >= target or r >= top:
+            return r, t
+        r = min(r + step, top)
 
 
 def identity_dm(tables: dict) -> dict:

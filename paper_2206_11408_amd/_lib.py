@@ -67,7 +67,7 @@ class TablesInfo(C.Structure):
         ("n_samples_used", C.c_int64), ("mu", C.c_double), ("sigma", C.c_double),
         ("mu_hat", C.c_double), ("sigma_hat", C.c_double), ("eps", C.c_double),
         ("eps_gate", C.c_double), ("gate_attached", C.c_int32),
-        ("edge_table_bytes", C.c_int64),
+        ("edge_table_bytes", C.c_int64), ("corr_xy", C.c_double),
     ]
 
 

@@ -310,6 +310,11 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
     t->mu_hat = mu_hat;
     t->sigma_hat = sigma_hat;
     t->eps = hsum[0] / ns;
+    // Pearson correlation of X and Y (the rank-selection rule of Supplementary E)
+    HIPCHK(launch_dm_sums(t->xy, ns, mu, mu_hat, 0, 3, sums.p, s));
+    HIPCHK(hipMemcpyAsync(hsum, sums.p, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    t->corr_xy = (var > 0 && var_hat > 0) ? (hsum[0] / ns) / std::sqrt(var * var_hat) : 0.0;
     if (p->dm_override) {
       t->mu = p->dm[0];
       t->sigma = p->dm[1];
@@ -386,6 +391,7 @@ int finger_tables_info_get(const finger_tables* th, finger_tables_info* info) {
   info->eps_gate = t->eps_gate;
   info->gate_attached = t->gate;
   info->edge_table_bytes = t->r > 0 ? (int64_t)(t->code_bytes + (size_t)t->n * t->deg * 8) : 0;
+  info->corr_xy = t->corr_xy;
   return ok();
 }
 

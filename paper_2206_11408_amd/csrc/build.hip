@@ -192,7 +192,8 @@ __global__ void __launch_bounds__(1024) k_dm_sums(const double* xy, int64_t ns, 
     const double x = xy[2 * i], y = xy[2 * i + 1];
     if (stage == 0) { a += x; b += y; }
     else if (stage == 1) { a += (x - mu) * (x - mu); b += (y - mu_hat) * (y - mu_hat); }
-    else { a += fabs((y - mu_hat) * scale + mu - x); }
+    else if (stage == 2) { a += fabs((y - mu_hat) * scale + mu - x); }
+    else { a += (x - mu) * (y - mu_hat); }
   }
   s0[threadIdx.x] = a;
   s1[threadIdx.x] = b;

@@ -73,6 +73,7 @@ struct Tables {
   int32_t qprep_cols = 0;          // r + npiv rounded up to 64
   // distribution matching constants
   double mu = 0, sigma = 1, mu_hat = 0, sigma_hat = 1, eps = 0;
+  double corr_xy = 0;              // Pearson correlation of the sampled X, Y
   // build samples kept for inspection
   int64_t nsamp = 0;
   int32_t* samples = nullptr;      // [nsamp][3]

@@ -234,3 +234,56 @@ def test_table1_extra_memory_formula():
         formula = (r["r"] + 2) * r["n"] * 2 * r["M"] * 4 / 1e9
         printed = r["finger_gb"] - r["hnsw_gb"]
         assert abs(formula - printed) / printed < 0.10, r
+
+
+def test_any_full_rank_orthonormal_basis_reproduces_x(c1_small):
+    """Cosines are invariant under rotations, so any orthonormal basis of
+    full rank gives Y = X: correlation 1 and no correction (Algorithm 2 with
+    a supplied basis, the hook the RPLSH comparison uses)."""
+    data, _, G, _ = c1_small
+    m = data.shape[1]
+    Q, _ = np.linalg.qr(np.random.default_rng(21).normal(size=(m, m)))
+    t = build(data, G, m, n_samples=3000, seed=2, basis=Q.T)
+    np.testing.assert_allclose(t["Y"], t["X"], atol=1e-12)
+    assert t["corr"] == pytest.approx(1.0, abs=1e-12)
+    assert t["eps"] < 1e-12
+
+
+def test_pearson_matches_numpy():
+    from oracle.build import pearson
+    rng = np.random.default_rng(3)
+    X = rng.normal(size=500)
+    Y = 0.3 * X + rng.normal(size=500)
+    assert pearson(X, Y) == pytest.approx(np.corrcoef(X, Y)[0, 1], rel=1e-12)
+    assert pearson(X, np.full(500, 2.0)) == 0.0
+
+
+def test_rank_rule_of_thumb(c1_small):
+    """Supplementary E: the chosen r is a multiple of 8, reaches the target
+    correlation, and r - 8 does not; unreachable targets stop at m."""
+    from oracle.build import select_rank
+    data, _, G, _ = c1_small
+    m = data.shape[1]
+    kw = dict(n_samples=4000, seed=3)
+    for target in (0.5, 0.7, 0.9):
+        r, t = select_rank(data, G, target=target, **kw)
+        assert r % 8 == 0 and 8 <= r <= m
+        assert t["corr"] >= target or r == m
+        if r > 8:
+            assert build(data, G, r - 8, **kw)["corr"] < target
+    r, t = select_rank(data, G, target=1.5, **kw)
+    assert r == m
+    r, _ = select_rank(data, G, target=-1.0, **kw)
+    assert r == 8
+
+
+def test_learned_basis_beats_random_projection(c1_small):
+    """Section 3.3 / the ablation: at equal rank the SVD basis tracks the
+    true residual angles better than random Gaussian projections."""
+    from workloads import gaussian_projection
+    data, _, G, _ = c1_small
+    svd = build(data, G, 8, n_samples=4000, seed=4)
+    rp = build(data, G, 8, n_samples=4000, seed=4,
+               basis=gaussian_projection(8, data.shape[1], 7))
+    assert svd["corr"] > rp["corr"]
+    assert svd["eps"] < rp["eps"]

@@ -11,6 +11,7 @@ from .gen import (  # noqa: F401
     WorkloadSpec,
     SPECS,
     gate_weights,
+    gaussian_projection,
     make_points,
 )
 from .graph import (  # noqa: F401

@@ -95,6 +95,13 @@ def gate_weights(in_dim: int, hidden: int, seed: int, scale: float = 0.1,
     return w.astype(np.float32)
 
 
+def gaussian_projection(rank: int, m: int, seed: int) -> np.ndarray:
+    """A seeded r x m matrix of independent N(0, 1) entries (float64): the
+    random projection of RPLSH, handed to both the library and the oracle
+    when the ablation swaps it in for the learned basis."""
+    return np.random.default_rng(seed).standard_normal((rank, m))
+
+
 def make_points(spec: WorkloadSpec) -> tuple[np.ndarray, np.ndarray]:
     """Return (data [n, m], queries [nq, m]) as C-contiguous float32."""
     rng = np.random.default_rng(spec.seed)
