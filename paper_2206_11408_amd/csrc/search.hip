@@ -434,6 +434,12 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   const int csub = l / cpr;
   const int ch = l - csub * cpr;
 
+  // edge-code chunks (pass 1, pass 2), zeroed once so that lanes whose slot
+  // is not loaded hold defined values; their dot products are masked out
+  Chunk<CODE> code, code2;
+  code.zero();
+  code2.zero();
+
   for (int64_t it = 0;; ++it) {
     int64_t qi;
     if (a.persistent) {
@@ -514,7 +520,6 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       int nb = -1;
       if (l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
       float al = 0.f, rh = 0.f, ccv = 0.f, pc0 = 0.f;
-      Chunk<CODE> code;
       if constexpr (MODE != FINGER_MODE_PLAIN) {
         if (screening) {
           if (csub < a.deg) {
@@ -549,13 +554,12 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           // with the adjacency row) and pass 2 (slot spp + csub, with its
           // alpha and rho).  BF16/FP8 codes of r <= 64 fit one pass.
           constexpr bool kPreload2 = CODE == FINGER_CODE_F32;
+          // (chunks of visited or padding slots keep stale values: their dot
+          // products are masked out)
           if constexpr (!PREFETCH) {
             if (csub < a.deg && ((newm >> csub) & 1ull))
               code.load(a.codes, ((int64_t)cur * a.deg + csub) * a.rpad + ch * kChunk);
-            else
-              code.zero();
           }
-          Chunk<CODE> code2;
           float al2 = 0.f, rh2 = 0.f;
           if (kPreload2 && a.spp < a.deg) {
             const int s2 = a.spp + csub;
@@ -565,8 +569,6 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
             }
             if (s2 < a.deg && ((newm >> s2) & 1ull))
               code2.load(a.codes, ((int64_t)cur * a.deg + s2) * a.rpad + ch * kChunk);
-            else
-              code2.zero();
           }
           // query side (Section 3.2 and Supplementary G): q.c from the exact
           // d2 of the centre, alpha_q, |q_res|^2, w = Pq - alpha_q P c
@@ -606,21 +608,12 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
             for (int nt = 0; nt < 4; ++nt) b1v[nt] = __shfl(base1, 16 * nt + (l & 15), 64);
           }
           bool skip_l = false;  // the decision for this lane's adjacency slot
-          for (int p0 = 0; p0 < a.deg; p0 += a.spp) {
+          // one screening pass over slots [p0, p0 + spp): this lane holds
+          // chunk ch of slot p0 + csub in cd, with that slot's alpha and rho
+          auto screen_pass = [&](int p0, const Chunk<CODE>& cd, float al, float rh) {
             const int slot = p0 + csub;
             const bool slot_new = slot < a.deg && ((newm >> slot) & 1ull);
-            if (kPreload2 && p0 == a.spp) {
-              al = al2;
-              rh = rh2;
-              code = code2;
-            } else if (p0 > 0) {
-              if (slot < a.deg) {
-                al = a.alpha[(int64_t)cur * a.deg + slot];
-                rh = a.rho[(int64_t)cur * a.deg + slot];
-              }
-              if (slot_new) code.load(a.codes, ((int64_t)cur * a.deg + slot) * a.rpad + ch * kChunk);
-              else code.zero();
-            }
+            const Chunk<CODE>& code = cd;
             const float dot = group_sum_rt(slot_new ? code.dot(wv + ch * kChunk) : 0.f, cpr);
             const float t_hat = dot * scl * inv_w;
             const float da = aq - al;
@@ -681,6 +674,24 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
             const bool in_pass = rel >= 0 && rel < a.spp;
             const int sk = __shfl(est > ub2 ? 1 : 0, (in_pass ? rel : 0) * cpr, 64);
             if (in_pass) skip_l = sk != 0;
+          };
+          screen_pass(0, code, al, rh);
+          if (a.spp < a.deg) {
+            if constexpr (kPreload2) {
+              screen_pass(a.spp, code2, al2, rh2);
+            }
+            // further passes (more slots than two passes hold) load as they go
+            for (int p0 = kPreload2 ? 2 * a.spp : a.spp; p0 < a.deg; p0 += a.spp) {
+              const int slot = p0 + csub;
+              float alx = 0.f, rhx = 0.f;
+              if (slot < a.deg) {
+                alx = a.alpha[(int64_t)cur * a.deg + slot];
+                rhx = a.rho[(int64_t)cur * a.deg + slot];
+              }
+              if (slot < a.deg && ((newm >> slot) & 1ull))
+                code.load(a.codes, ((int64_t)cur * a.deg + slot) * a.rpad + ch * kChunk);
+              screen_pass(p0, code, alx, rhx);
+            }
           }
           // back in adjacency lanes
           const bool keep = isnew && !skip_l;
