@@ -32,16 +32,39 @@ __device__ __forceinline__ float shfl_xor_f(float v, int m) { return __shfl_xor(
 __device__ __forceinline__ int shfl_i(int v, int src) { return __shfl(v, src, 64); }
 __device__ __forceinline__ float shfl_f(float v, int src) { return __shfl(v, src, 64); }
 
+// DPP lane moves inside rows of 16 lanes (no LDS traffic): quad_perm
+// [1,0,3,2] and [2,3,0,1] swap neighbours and pairs, row_half_mirror maps
+// lane i to 7 - i within 8, row_mirror i to 15 - i within 16.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 // sum over aligned groups of G lanes (G a power of two <= 64); every lane of
-// the group gets the total
+// the group gets the total.  Within 16 lanes each step adds a DPP-moved copy
+// (after the quad steps every lane holds its quad's sum, so the mirrors pair
+// whole quads and then whole 8-lane halves); wider groups add 16- and
+// 32-lane swaps.
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-  for (int s = G / 2; s >= 1; s >>= 1) v += shfl_xor_f(v, s);
+  if constexpr (G >= 2) v += dpp_f<kDppXor1>(v);
+  if constexpr (G >= 4) v += dpp_f<kDppXor2>(v);
+  if constexpr (G >= 8) v += dpp_f<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp_f<kDppMirror>(v);
+  if constexpr (G >= 32) v += shfl_xor_f(v, 16);
+  if constexpr (G >= 64) v += shfl_xor_f(v, 32);
   return v;
 }
 
-__device__ __forceinline__ float wave_sum(float v) { return group_sum<64>(v); }
+// sum over the wave, as a wave-uniform (scalar) value
+__device__ __forceinline__ float wave_sum(float v) {
+  v = group_sum<16>(v);
+  return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
 
 // uniform (scalar) copy of a wave-uniform value
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }

@@ -41,10 +41,11 @@ constexpr uint32_t kExpanded = 0x80000000u;
 // FINGER search that also writes the gate-training log (internal mode)
 constexpr int kModeLog = 3;
 constexpr int kLdsProbes = 24;
-// code elements one lane holds: 64 bytes of fp32 or bf16, 32 bytes of fp8
+// code elements one lane holds: 32 (128 bytes of fp32, 64 of bf16, 32 of
+// fp8), so a rank-64 code is two lanes and a screen of 32 slots one pass
 template <int CODE>
-constexpr int chunk_elems() { return CODE == FINGER_CODE_F32 ? 16 : 32; }
-__host__ __device__ inline int chunk_elems_rt(int code) { return code == FINGER_CODE_F32 ? 16 : 32; }
+constexpr int chunk_elems() { return 32; }
+__host__ __device__ inline int chunk_elems_rt(int) { return 32; }
 
 struct KArgs {
   const float* data;
@@ -132,15 +133,15 @@ struct Chunk;
 
 template <>
 struct Chunk<FINGER_CODE_F32> {
-  float4 v[4];
+  float4 v[8];
   __device__ __forceinline__ void load(const void* base, int64_t elem) {
     const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(base) + elem);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = p[i];
+    for (int i = 0; i < 8; ++i) v[i] = p[i];
   }
   __device__ __forceinline__ void zero() {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = 0; i < 8; ++i) v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   __device__ __forceinline__ float at(int e) const {
     const float4 q = v[e >> 2];
@@ -151,7 +152,7 @@ struct Chunk<FINGER_CODE_F32> {
     const float4* w4 = reinterpret_cast<const float4*>(w);
     float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
       const float4 a = w4[i];
       s += a.x * v[i].x + a.y * v[i].y + a.z * v[i].z + a.w * v[i].w;
     }
@@ -228,7 +229,12 @@ struct Chunk<FINGER_CODE_FP8E4M3> {
 
 // sum over aligned groups of g lanes, g a runtime power of two <= 64
 __device__ __forceinline__ float group_sum_rt(float v, int g) {
-  for (int s = g >> 1; s >= 1; s >>= 1) v += shfl_xor_f(v, s);
+  if (g >= 2) v += dpp_f<kDppXor1>(v);
+  if (g >= 4) v += dpp_f<kDppXor2>(v);
+  if (g >= 8) v += dpp_f<kDppHalfMirror>(v);
+  if (g >= 16) v += dpp_f<kDppMirror>(v);
+  if (g >= 32) v += shfl_xor_f(v, 16);
+  if (g >= 64) v += shfl_xor_f(v, 32);
   return v;
 }
 
@@ -434,11 +440,10 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   const int csub = l / cpr;
   const int ch = l - csub * cpr;
 
-  // edge-code chunks (pass 1, pass 2), zeroed once so that lanes whose slot
-  // is not loaded hold defined values; their dot products are masked out
-  Chunk<CODE> code, code2;
+  // edge-code chunk, zeroed once so that lanes whose slot is not loaded hold
+  // defined values; their dot products are masked out
+  Chunk<CODE> code;
   code.zero();
-  code2.zero();
 
   for (int64_t it = 0;; ++it) {
     int64_t qi;
@@ -548,27 +553,12 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           // 4. screening
           n_scr += S;
           ++n_prep;
-          // code requests for the new slots, issued together so that the
-          // screen costs one round trip when fp32 codes take two passes
-          // (r = 64: 16 slots per pass): pass 1 (slot csub, unless requested
-          // with the adjacency row) and pass 2 (slot spp + csub, with its
-          // alpha and rho).  BF16/FP8 codes of r <= 64 fit one pass.
-          constexpr bool kPreload2 = CODE == FINGER_CODE_F32;
-          // (chunks of visited or padding slots keep stale values: their dot
-          // products are masked out)
+          // codes of the new slots of the first pass (slot csub), unless
+          // requested with the adjacency row; chunks of visited or padding
+          // slots keep stale values, their dot products are masked out
           if constexpr (!PREFETCH) {
             if (csub < a.deg && ((newm >> csub) & 1ull))
               code.load(a.codes, ((int64_t)cur * a.deg + csub) * a.rpad + ch * kChunk);
-          }
-          float al2 = 0.f, rh2 = 0.f;
-          if (kPreload2 && a.spp < a.deg) {
-            const int s2 = a.spp + csub;
-            if (s2 < a.deg) {
-              al2 = a.alpha[(int64_t)cur * a.deg + s2];
-              rh2 = a.rho[(int64_t)cur * a.deg + s2];
-            }
-            if (s2 < a.deg && ((newm >> s2) & 1ull))
-              code2.load(a.codes, ((int64_t)cur * a.deg + s2) * a.rpad + ch * kChunk);
           }
           // query side (Section 3.2 and Supplementary G): q.c from the exact
           // d2 of the centre, alpha_q, |q_res|^2, w = Pq - alpha_q P c
@@ -677,11 +667,8 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           };
           screen_pass(0, code, al, rh);
           if (a.spp < a.deg) {
-            if constexpr (kPreload2) {
-              screen_pass(a.spp, code2, al2, rh2);
-            }
-            // further passes (more slots than two passes hold) load as they go
-            for (int p0 = kPreload2 ? 2 * a.spp : a.spp; p0 < a.deg; p0 += a.spp) {
+            // further passes (r > 64: more slots than one pass holds) load as they go
+            for (int p0 = a.spp; p0 < a.deg; p0 += a.spp) {
               const int slot = p0 + csub;
               float alx = 0.f, rhx = 0.f;
               if (slot < a.deg) {
