@@ -73,6 +73,16 @@ def estimate(q, c, D, tables: dict, codes=None) -> np.ndarray:
     return combine(p, dm_map(p["t_hat"], tables))
 
 
+def estimate_ip(q, c, D, tables: dict, codes=None) -> np.ndarray:
+    """Supplementary A for inner products: q.d = q_proj.d_proj + q_res.d_res
+    with q_proj.d_proj = alpha_q alpha_d (c.c) and q_res.d_res replaced by
+    ||q_res|| ||d_res|| t as in Algorithm 3.  Returned negated (the search
+    minimises -q.d), so adding eps to t again lowers the estimate."""
+    p = parts(q, c, D, tables["P"], codes)
+    t = dm_map(p["t_hat"], tables)
+    return -(p["alpha_q"] * p["alpha_d"] * p["cc"] + p["rq"] * p["rd"] * t)
+
+
 def true_cosine(q, c, D) -> np.ndarray:
     """cos(q_res, d_res), the quantity Algorithm 3 estimates (0 if either
     residual is zero)."""

@@ -12,6 +12,22 @@ def sqdist(x: np.ndarray, Y: np.ndarray) -> np.ndarray:
     return (diff * diff).sum(axis=-1)
 
 
+def ipdist(x: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Inner-product "distance" -q.y for maximum inner-product search
+    (Supplementary A): smaller is better, so the search's ordering and
+    admission rule apply unchanged."""
+    return -(np.asarray(Y, dtype=np.float64) @ np.asarray(x, dtype=np.float64))
+
+
+def dist(x: np.ndarray, Y: np.ndarray, metric: str = "l2") -> np.ndarray:
+    """Squared L2 (``"l2"``) or negated inner product (``"ip"``)."""
+    if metric == "l2":
+        return sqdist(x, Y)
+    if metric == "ip":
+        return ipdist(x, Y)
+    raise ValueError(metric)
+
+
 def normalize_rows(X: np.ndarray) -> np.ndarray:
     """Unit-normalize rows in float64 (angular distance is L2 on unit vectors,
     Supplementary A); zero rows stay zero."""
@@ -20,8 +36,9 @@ def normalize_rows(X: np.ndarray) -> np.ndarray:
     return np.where(nrm > 0, X / np.where(nrm > 0, nrm, 1.0), 0.0)
 
 
-def brute_force_knn(data: np.ndarray, queries: np.ndarray, k: int):
-    """The K closest points of ``data`` to each query, ordered by (d2, id).
+def brute_force_knn(data: np.ndarray, queries: np.ndarray, k: int, metric: str = "l2"):
+    """The K closest points of ``data`` to each query, ordered by (d2, id)
+    (for ``metric="ip"``: by (-q.x, id), the K largest inner products).
 
     Returns (ids int64 [nq, k], d2 float64 [nq, k]); if k > n the tail is
     padded with id -1 and d2 +inf."""
@@ -33,7 +50,7 @@ def brute_force_knn(data: np.ndarray, queries: np.ndarray, k: int):
     d2 = np.full((nq, k), np.inf, dtype=np.float64)
     idx = np.arange(n)
     for i in range(nq):
-        d = sqdist(queries[i], data)
+        d = dist(queries[i], data, metric)
         order = np.lexsort((idx, d))[:k]
         ids[i, :order.size] = order
         d2[i, :order.size] = d[order]

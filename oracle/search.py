@@ -39,7 +39,8 @@ import math
 import numpy as np
 
 from .estimate import estimate as finger_estimate
-from .knn import sqdist
+from .estimate import estimate_ip as finger_estimate_ip
+from .knn import dist
 
 COUNTER_NAMES = ("expansions", "exact", "screened", "skipped", "visited", "preps")
 
@@ -77,7 +78,7 @@ class _TopList:
 def search(data: np.ndarray, graph: np.ndarray, q: np.ndarray, entry: int,
            ef: int, k: int, mode: str = "plain", tables: dict | None = None,
            warmup: int = 5, ub_mode: str = "batched", estimator=None,
-           record: list | None = None):
+           record: list | None = None, metric: str = "l2"):
     """One query.  Returns (ids int64 [k], d2 float64 [k], counters dict,
     margin) where ids/d2 are the first k keys of T (padded with -1/+inf)
     and margin is the smallest |est - ub^2| / ub^2 over all screening
@@ -85,13 +86,15 @@ def search(data: np.ndarray, graph: np.ndarray, q: np.ndarray, entry: int,
 
     ``estimator(q, c_id, nbr_ids, ub2) -> est`` overrides Algorithm 3 (used
     for quantized codes and the learned gate).  ``record``, if a list,
-    receives one tuple (cur, nbr_ids, est, ub2) per screened expansion."""
+    receives one tuple (cur, nbr_ids, est, ub2) per screened expansion.
+    ``metric="ip"`` searches by -q.d (maximum inner product, Supplementary
+    A) with the inner-product estimate; the margin is then relative to |ub|."""
     assert mode in ("plain", "finger")
     ef_eff = max(int(ef), int(k))
     q = np.asarray(q, dtype=np.float64)
     T = _TopList(ef_eff)
     V = {int(entry)}
-    T.admit(float(sqdist(q, data[entry])), int(entry))
+    T.admit(float(dist(q, data[entry], metric)), int(entry))
     cnt = dict.fromkeys(COUNTER_NAMES, 0)
     cnt["exact"] = 1
     margin = math.inf
@@ -99,6 +102,8 @@ def search(data: np.ndarray, graph: np.ndarray, q: np.ndarray, entry: int,
     def est_of(cur, ids, ub2):
         if estimator is not None:
             return np.asarray(estimator(q, cur, ids, ub2), dtype=np.float64)
+        if metric == "ip":
+            return finger_estimate_ip(q, data[cur], data[ids], tables)
         return finger_estimate(q, data[cur], data[ids], tables)
 
     while True:
@@ -127,13 +132,13 @@ def search(data: np.ndarray, graph: np.ndarray, q: np.ndarray, entry: int,
                 cnt["preps"] += 1
                 keep = est <= ub2
                 cnt["skipped"] += int((~keep).sum())
-                if ub2 > 0:
-                    margin = min(margin, float(np.min(np.abs(est - ub2)) / ub2))
+                if ub2 != 0:
+                    margin = min(margin, float(np.min(np.abs(est - ub2)) / abs(ub2)))
                 if record is not None:
                     record.append((cur, np.array(new), est, ub2))
                 survivors = [nb for nb, kp in zip(new, keep) if kp]
             if survivors:
-                d2 = sqdist(q, data[survivors])
+                d2 = dist(q, data[survivors], metric)
                 cnt["exact"] += len(survivors)
                 for nb, dd in zip(survivors, d2):
                     T.admit(dd, nb)
@@ -143,12 +148,12 @@ def search(data: np.ndarray, graph: np.ndarray, q: np.ndarray, entry: int,
                     ub2 = T.worst()[0]
                     est = float(est_of(cur, [nb], ub2)[0])
                     cnt["screened"] += 1
-                    if ub2 > 0:
-                        margin = min(margin, abs(est - ub2) / ub2)
+                    if ub2 != 0:
+                        margin = min(margin, abs(est - ub2) / abs(ub2))
                     if est > ub2:
                         cnt["skipped"] += 1
                         continue
-                dd = float(sqdist(q, data[nb]))
+                dd = float(dist(q, data[nb], metric)[()])
                 cnt["exact"] += 1
                 T.admit(dd, nb)
         else:
@@ -162,15 +167,16 @@ def search(data: np.ndarray, graph: np.ndarray, q: np.ndarray, entry: int,
     return ids, d2, cnt, margin
 
 
-def pivot_entries(queries: np.ndarray, data: np.ndarray, pivots: np.ndarray) -> np.ndarray:
+def pivot_entries(queries: np.ndarray, data: np.ndarray, pivots: np.ndarray,
+                  metric: str = "l2") -> np.ndarray:
     """Start point p of each query (Algorithm 1's input) when it is chosen
-    among pivot nodes: the pivot at the smallest exact squared distance,
-    ties to the earlier pivot in the list.  (A flat stand-in for the upper
-    layers of the HNSW graph the paper searches.)"""
+    among pivot nodes: the pivot at the smallest exact distance (squared L2,
+    or -q.p), ties to the earlier pivot in the list.  (A flat stand-in for
+    the upper layers of the HNSW graph the paper searches.)"""
     P = np.asarray(data[pivots], dtype=np.float64)
     out = np.empty(np.atleast_2d(queries).shape[0], dtype=np.int64)
     for i, q in enumerate(np.atleast_2d(queries)):
-        out[i] = pivots[int(np.argmin(sqdist(q, P)))]
+        out[i] = pivots[int(np.argmin(dist(q, P, metric)))]
     return out
 
 
