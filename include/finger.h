@@ -49,9 +49,15 @@ typedef enum {
 
 typedef enum {
   FINGER_L2 = 0,          /* squared Euclidean distance */
-  FINGER_ANGULAR = 1      /* squared L2 between unit-normalized vectors
+  FINGER_ANGULAR = 1,     /* squared L2 between unit-normalized vectors
                              (Supplementary A: normalize, then the same
                              decomposition); 1 - cos = d2 / 2 */
+  FINGER_IP = 2           /* maximum inner product: the "distance" is -q.x,
+                             so results are the K largest inner products and
+                             reported values are their negatives.  The
+                             estimate is Supplementary A's q_proj.d_proj +
+                             |q_res| |d_res| t, negated.  The learned gate
+                             (and its feature log) is for L2 only. */
 } finger_metric;
 
 typedef enum {
@@ -333,7 +339,9 @@ FINGER_API int finger_exact_knn(const float* data, int64_t n, int32_t m,
 
 /* Weight layout (float, host): W1 [H][in], b1 [H], W2 [H][H], b2 [H],
  * W3 [H], b3 [1]; 1 <= H <= 64 and in == FINGER_GATE_FEATURES(rank).  The
- * handle keeps a bf16 copy used by the search kernel.  Synchronous. */
+ * handle keeps a bf16 copy used by the search kernel.  Synchronous.
+ * Errors: EINVAL (NULL arguments, rank-0 or FINGER_IP handle, in_dim or H
+ * out of range), EDEVICE (allocation or copy failed). */
 FINGER_API int finger_gate_attach(finger_tables* t, const float* weights /* host */,
                        int32_t in_dim, int32_t hidden, double eps_gate);
 

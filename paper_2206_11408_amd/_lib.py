@@ -18,7 +18,7 @@ FINGER_EINTERNAL = -6
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENODEV",
                 -5: "EOVERFLOW", -6: "EINTERNAL"}
 
-L2, ANGULAR = 0, 1
+L2, ANGULAR, IP = 0, 1, 2
 CODE_F32, CODE_BF16, CODE_FP8E4M3 = 0, 1, 2
 MODE_PLAIN, MODE_FINGER, MODE_GATED = 0, 1, 2
 SIGMA_STD, SIGMA_VARIANCE = 0, 1

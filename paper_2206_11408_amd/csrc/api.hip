@@ -174,7 +174,7 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
     return fail(FINGER_EINVAL, "rank = %d out of range [0, min(m, %d)]", p->rank, kMaxRank);
   if (p->code_type < FINGER_CODE_F32 || p->code_type > FINGER_CODE_FP8E4M3)
     return fail(FINGER_EINVAL, "unknown code_type %d", p->code_type);
-  if (p->metric != FINGER_L2 && p->metric != FINGER_ANGULAR)
+  if (p->metric != FINGER_L2 && p->metric != FINGER_ANGULAR && p->metric != FINGER_IP)
     return fail(FINGER_EINVAL, "unknown metric %d", p->metric);
   if (p->sigma_mode != FINGER_SIGMA_STD && p->sigma_mode != FINGER_SIGMA_VARIANCE)
     return fail(FINGER_EINVAL, "unknown sigma_mode %d", p->sigma_mode);
@@ -359,8 +359,11 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
       const size_t np = (size_t)pivot_pad_rows(t->npiv);
       if ((st = dev_alloc(reinterpret_cast<void**>(&t->piv_norm), np * 4, "pivot norms")) != FINGER_OK) return st;
       HIPCHK(hipMemsetAsync(t->piv_norm, 0, np * 4, s));
-      HIPCHK(hipMemcpyAsync(t->piv_norm, t->qprep_Bnorm + rcols, (size_t)t->npiv * 4,
-                            hipMemcpyDeviceToDevice, s));
+      // pivot scores |p|^2 - 2 q.p rank by L2; with zero norms, -2 q.p ranks
+      // by inner product
+      if (t->metric != FINGER_IP)
+        HIPCHK(hipMemcpyAsync(t->piv_norm, t->qprep_Bnorm + rcols, (size_t)t->npiv * 4,
+                              hipMemcpyDeviceToDevice, s));
     }
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -457,6 +460,8 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
     return fail(FINGER_EINVAL, "unknown mode %d", p->mode);
   if (p->mode != FINGER_MODE_PLAIN && t->r == 0)
     return fail(FINGER_EINVAL, "FINGER modes need a handle built with rank > 0");
+  if (t->metric == FINGER_IP && (p->mode == FINGER_MODE_GATED || p->log_features != nullptr))
+    return fail(FINGER_EINVAL, "the learned gate and its feature log are for L2 and angular only");
   if (p->mode == FINGER_MODE_GATED && !t->gate)
     return fail(FINGER_EINVAL, "gated mode needs finger_gate_attach first");
   if (nq < 0) return fail(FINGER_EINVAL, "nq < 0");
@@ -654,7 +659,8 @@ int finger_exact_knn(const float* data, int64_t n, int32_t m, const float* queri
   size_t need = 0;
   int st = finger_exact_knn_workspace_size(n, m, nq, k, &need);
   if (st != FINGER_OK) return st;
-  if (metric != FINGER_L2 && metric != FINGER_ANGULAR) return fail(FINGER_EINVAL, "unknown metric %d", metric);
+  if (metric != FINGER_L2 && metric != FINGER_ANGULAR && metric != FINGER_IP)
+    return fail(FINGER_EINVAL, "unknown metric %d", metric);
   if (nq == 0) return ok();
   if (!data || !queries || !out_ids || !out_dist) return fail(FINGER_EINVAL, "NULL pointer");
   if (((reinterpret_cast<uintptr_t>(data) | reinterpret_cast<uintptr_t>(queries)) & 15u) != 0)
@@ -694,6 +700,7 @@ int finger_gate_attach(finger_tables* th, const float* weights, int32_t in_dim, 
   if (th == nullptr || weights == nullptr) return fail(FINGER_EINVAL, "NULL argument");
   Tables* t = reinterpret_cast<Tables*>(th);
   if (t->r == 0) return fail(FINGER_EINVAL, "rank-0 handle cannot take a gate");
+  if (t->metric == FINGER_IP) return fail(FINGER_EINVAL, "the learned gate is for L2 and angular only");
   if (in_dim != FINGER_GATE_FEATURES(t->r))
     return fail(FINGER_EINVAL, "in_dim = %d, expected 2r+4 = %d", in_dim, FINGER_GATE_FEATURES(t->r));
   if (hidden < 1 || hidden > 64) return fail(FINGER_EINVAL, "hidden = %d out of range [1, 64]", hidden);

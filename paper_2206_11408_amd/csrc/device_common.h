@@ -72,12 +72,21 @@ __device__ __forceinline__ float uniform_f(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// (d2, id) keys packed so that unsigned comparison is the lexicographic
-// order: d2 >= 0 is monotone in its bit pattern; ids are < 2^31.
-__device__ __forceinline__ uint64_t make_key(float d2, int id) {
-  return ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)id;
+// (d, id) keys packed so that unsigned comparison is the lexicographic
+// order: the distance's bits map to an unsigned value of the same order
+// (negative values, from the inner-product metric, included; -0 is folded
+// into +0 so that equal distances tie on the id); ids are < 2^31.
+__device__ __forceinline__ uint32_t order_bits(float f) {
+  const uint32_t u = __float_as_uint(f + 0.0f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
-__device__ __forceinline__ float key_d2(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ float order_bits_inv(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+__device__ __forceinline__ uint64_t make_key(float d2, int id) {
+  return ((uint64_t)order_bits(d2) << 32) | (uint32_t)id;
+}
+__device__ __forceinline__ float key_d2(uint64_t k) { return order_bits_inv((uint32_t)(k >> 32)); }
 __device__ __forceinline__ int key_id(uint64_t k) { return (int)(uint32_t)k; }
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {

@@ -162,12 +162,6 @@ __device__ __forceinline__ uint64_t sort16(uint64_t v) {
   return v;
 }
 
-// float -> unsigned with the same order (negative scores included)
-__device__ __forceinline__ uint32_t ordered_bits(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
 __device__ __forceinline__ b8v load_query_frag(const float* __restrict__ Q, int64_t nq, int m,
                                               int64_t row, int k) {
   float v[8];
@@ -197,7 +191,7 @@ __device__ __forceinline__ void fold_tile(const f4v& acc, int col, int npiv, flo
   if (col >= npiv) return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const uint64_t k = ((uint64_t)ordered_bits(pn - 2.f * acc[v]) << 32) | (uint32_t)col;
+    const uint64_t k = ((uint64_t)order_bits(pn - 2.f * acc[v]) << 32) | (uint32_t)col;
     best[v] = k < best[v] ? k : best[v];
   }
 }
@@ -312,7 +306,7 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
 __global__ void k_qfinish(const float* __restrict__ Q, int64_t nq, int m,
                           const float* __restrict__ PF, const int32_t* __restrict__ piv_ids,
                           int npiv, const uint64_t* __restrict__ cand, float* __restrict__ qq,
-                          int32_t* __restrict__ entries) {
+                          int32_t* __restrict__ entries, int ip) {
   const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + uniform_i(threadIdx.x / 64);
   if (q >= nq) return;
   const int l = threadIdx.x & 63;
@@ -332,10 +326,17 @@ __global__ void k_qfinish(const float* __restrict__ Q, int64_t nq, int m,
   if (valid) {
     const float4* p4 = reinterpret_cast<const float4*>(PF + (int64_t)col * m);
     const float4* q4 = reinterpret_cast<const float4*>(qv);
-    for (int j = part; j < m / 4; j += 4) {
-      const float4 x = q4[j], y = p4[j];
-      const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z, dw = x.w - y.w;
-      d += dx * dx + dy * dy + dz * dz + dw * dw;
+    if (ip) {
+      for (int j = part; j < m / 4; j += 4) {
+        const float4 x = q4[j], y = p4[j];
+        d -= x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+      }
+    } else {
+      for (int j = part; j < m / 4; j += 4) {
+        const float4 x = q4[j], y = p4[j];
+        const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z, dw = x.w - y.w;
+        d += dx * dx + dy * dy + dz * dz + dw * dw;
+      }
     }
   }
   d += shfl_xor_f(d, 1);
@@ -416,7 +417,7 @@ hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float*
   const int wpb = 4;
   hipLaunchKernelGGL(k_qfinish, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), 0, s, Q,
                      nq, t.m, t.qprep_B + (int64_t)rcols * t.m, t.piv_ids, t.npiv, cand, qq,
-                     piv ? entries : nullptr);
+                     piv ? entries : nullptr, t.metric == FINGER_IP ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -431,7 +432,7 @@ constexpr int kKnnSlack = 32;
 __global__ void __launch_bounds__(256) k_knn_tiles(const float* Q, int64_t nq, const float* X,
                                                    int64_t n, int K, const float* qn,
                                                    const float* xn, int KK, int64_t chunk,
-                                                   uint64_t* out, int nchunks) {
+                                                   uint64_t* out, int nchunks, int ip) {
   extern __shared__ __align__(16) char smem[];
   float* As = reinterpret_cast<float*>(smem);
   float* Bs = As + BM * LDT;
@@ -460,7 +461,8 @@ __global__ void __launch_bounds__(256) k_knn_tiles(const float* Q, int64_t nq, c
           const int cl = wc + 16 * j + (l & 15);
           const int64_t row = r0 + rr, col = c0 + cl;
           float d = __int_as_float(0x7f800000);
-          if (row < nq && col < cend) d = fmaxf(qn[row] + xn[col] - 2.f * acc[i][j][v], 0.f);
+          if (row < nq && col < cend)
+            d = ip ? -acc[i][j][v] : fmaxf(qn[row] + xn[col] - 2.f * acc[i][j][v], 0.f);
           Ct[rr * 65 + cl] = d;
         }
     __syncthreads();
@@ -522,7 +524,7 @@ __global__ void __launch_bounds__(256) k_knn_tiles(const float* Q, int64_t nq, c
 // Per query (one wave): gather the chunk lists, keep the KK best keys,
 // re-rank them by direct float32 differences and emit the best k by (d2, id).
 __global__ void k_knn_final(const float* Q, int64_t nq, const float* X, int m, int k, int KK,
-                            int nchunks, const uint64_t* cand, int32_t* ids, float* dist) {
+                            int nchunks, const uint64_t* cand, int32_t* ids, float* dist, int ip) {
   extern __shared__ __align__(16) char smem[];
   const int wib = threadIdx.x / 64, l = threadIdx.x & 63;
   const int64_t q = (int64_t)blockIdx.x * (blockDim.x / 64) + wib;
@@ -563,7 +565,10 @@ __global__ void k_knn_final(const float* Q, int64_t nq, const float* X, int m, i
     const int id = key_id(sel[t]);
     const float* xv = X + (int64_t)id * m;
     float d = 0.f;
-    for (int j = l; j < m; j += 64) { float u = qv[j] - xv[j]; d += u * u; }
+    if (ip)
+      for (int j = l; j < m; j += 64) d -= qv[j] * xv[j];
+    else
+      for (int j = l; j < m; j += 64) { float u = qv[j] - xv[j]; d += u * u; }
     d = wave_sum(d);
     if (l == 0) ex[t] = make_key(d, id);
   }
@@ -609,7 +614,6 @@ size_t exact_knn_ws_bytes(int64_t n, int m, int64_t nq, int k) {
 hipError_t launch_exact_knn(const float* data, int64_t n, int m, const float* Q, int64_t nq,
                             int k, int metric, int32_t* ids, float* dist, void* ws,
                             hipStream_t s) {
-  (void)metric;
   if (nq == 0) return hipSuccess;
   const int KK = k + kKnnSlack;
   const int nch = knn_chunks(n, nq);
@@ -631,7 +635,7 @@ hipError_t launch_exact_knn(const float* data, int64_t n, int m, const float* Q,
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)nch, (unsigned)((nq + BM - 1) / BM));
   hipLaunchKernelGGL(k_knn_tiles, grid, dim3(256), lds, s, Q, nq, data, n, m, qn, xn, KK, chunk,
-                     cand, nch);
+                     cand, nch, metric == FINGER_IP ? 1 : 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int wpb = 2;
@@ -640,7 +644,7 @@ hipError_t launch_exact_knn(const float* data, int64_t n, int m, const float* Q,
                           hipFuncAttributeMaxDynamicSharedMemorySize, flds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_knn_final, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(64 * wpb), flds, s,
-                     Q, nq, data, m, k, KK, nch, cand, ids, dist);
+                     Q, nq, data, m, k, KK, nch, cand, ids, dist, metric == FINGER_IP ? 1 : 0);
   return hipGetLastError();
 }
 

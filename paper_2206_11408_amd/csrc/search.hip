@@ -80,6 +80,7 @@ struct KArgs {
   // scheduling / scratch
   int32_t* queue;
   int persistent;
+  int ip;     // inner-product metric: distance -q.x
   int32_t* spill;
   int spill_slots;
   int vis_cap;
@@ -285,13 +286,23 @@ __device__ __forceinline__ float exact_dists(const KArgs& a, const float4* qv, c
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
       float acc = 0.f;
+      if (a.ip) {
+        // inner-product metric: the distance is -q.x
 #pragma unroll
-      for (int t = 0; t < T4; ++t) {
-        const int j = lg + G * t;
-        const float4 q = qlds != nullptr ? (j < a.m4 ? qlds[j] : make_float4(0.f, 0.f, 0.f, 0.f)) : qv[t];
-        const float dx = q.x - xv[h][t].x, dy = q.y - xv[h][t].y;
-        const float dz = q.z - xv[h][t].z, dw = q.w - xv[h][t].w;
-        acc += dx * dx + dy * dy + dz * dz + dw * dw;
+        for (int t = 0; t < T4; ++t) {
+          const int j = lg + G * t;
+          const float4 q = qlds != nullptr ? (j < a.m4 ? qlds[j] : make_float4(0.f, 0.f, 0.f, 0.f)) : qv[t];
+          acc -= q.x * xv[h][t].x + q.y * xv[h][t].y + q.z * xv[h][t].z + q.w * xv[h][t].w;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < T4; ++t) {
+          const int j = lg + G * t;
+          const float4 q = qlds != nullptr ? (j < a.m4 ? qlds[j] : make_float4(0.f, 0.f, 0.f, 0.f)) : qv[t];
+          const float dx = q.x - xv[h][t].x, dy = q.y - xv[h][t].y;
+          const float dz = q.z - xv[h][t].z, dw = q.w - xv[h][t].w;
+          acc += dx * dx + dy * dy + dz * dz + dw * dw;
+        }
       }
       acc = group_sum<G>(acc);
       // vector p0 + h NPP + s sits in lanes [s G, s G + G); lane p0 + h NPP + s takes it
@@ -562,7 +573,8 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           }
           // query side (Section 3.2 and Supplementary G): q.c from the exact
           // d2 of the centre, alpha_q, |q_res|^2, w = Pq - alpha_q P c
-          const float qc = 0.5f * (qq + ccv - dcur);
+          // (inner-product metric: T holds -q.c itself)
+          const float qc = a.ip ? -dcur : 0.5f * (qq + ccv - dcur);
           const float aq = ccv > 0.f ? qc / ccv : 0.f;
           const float rq2 = fmaxf(qq - aq * qc, 0.f);
           const float rq = sqrtf(rq2);
@@ -657,7 +669,9 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
             } else {
               t = (t_hat - a.mu_hat) * a.dm_scale + a.mu + a.eps;
             }
-            const float est = proj + rq2 + rh * rh - 2.f * rq * rh * t;
+            // Eq. 2 (L2), or -(q_proj.d_proj + |q_res| |d_res| t) (inner product)
+            const float est = a.ip ? -(aq * al * ccv + rq * rh * t)
+                                   : proj + rq2 + rh * rh - 2.f * rq * rh * t;
             // skip iff the estimate exceeds ub (both squared); slot s of this
             // pass is decided in lane (s - p0) cpr and handed to lane s
             const int rel = l - p0;
@@ -872,6 +886,7 @@ int wave_bytes(int ef_max, int vis_cap, int r, int m, int gate_in) {
 }
 
 void fill_common(KArgs& a, const Tables& t) {
+  a.ip = t.metric == FINGER_IP ? 1 : 0;
   a.data = t.data;
   a.graph = t.graph;
   a.n = t.n;
@@ -976,13 +991,17 @@ __global__ void k_estimate_edges(KArgs a, const int32_t* qi, const int32_t* ci,
   float acc = 0.f;
   for (int j = l; j < a.m4; j += 64) {
     const float4 x = q4[j], y = c4[j];
-    const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z, dw = x.w - y.w;
-    acc += dx * dx + dy * dy + dz * dz + dw * dw;
+    if (a.ip) {
+      acc -= x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+    } else {
+      const float dx = x.x - y.x, dy = x.y - y.y, dz = x.z - y.z, dw = x.w - y.w;
+      acc += dx * dx + dy * dy + dz * dz + dw * dw;
+    }
   }
   const float dcur = wave_sum(acc);
   const float qq = a.qq[q];
   const float ccv = a.cc[c];
-  const float qc = 0.5f * (qq + ccv - dcur);
+  const float qc = a.ip ? -dcur : 0.5f * (qq + ccv - dcur);
   const float aq = ccv > 0.f ? qc / ccv : 0.f;
   const float rq2 = fmaxf(qq - aq * qc, 0.f);
   const float rq = sqrtf(rq2);
@@ -1010,7 +1029,7 @@ __global__ void k_estimate_edges(KArgs a, const int32_t* qi, const int32_t* ci,
   const float t = (t_hat - a.mu_hat) * a.dm_scale + a.mu + a.eps;
   const float da = aq - ad;
   if (l == 0) {
-    est[item] = da * da * ccv + rq2 + rd * rd - 2.f * rq * rd * t;
+    est[item] = a.ip ? -(aq * ad * ccv + rq * rd * t) : da * da * ccv + rq2 + rd * rd - 2.f * rq * rd * t;
     that[item] = t_hat;
   }
 }
