@@ -30,6 +30,10 @@ set.  Readings of the pseudo-code:
   ``ub_mode="sequential"`` follows Algorithm 4 literally: neighbours in
   stored order, ub refreshed after each admission.
 * Estimates and ub are compared as squared distances.
+
+Start points: the nearest of a set of pivot nodes (``pivot_entries``) or the
+greedy descent through the upper layers of an HNSW-style hierarchy
+(``descend``), with the same (d, id) keys.
 """
 from __future__ import annotations
 
@@ -178,6 +182,50 @@ def pivot_entries(queries: np.ndarray, data: np.ndarray, pivots: np.ndarray,
     for i, q in enumerate(np.atleast_2d(queries)):
         out[i] = pivots[int(np.argmin(dist(q, P, metric)))]
     return out
+
+
+def descend(q: np.ndarray, data: np.ndarray, levels: np.ndarray, upper: np.ndarray,
+            metric: str = "l2") -> tuple[int, int]:
+    """Start point p of Algorithm 1 as an HNSW graph supplies it: the greedy
+    descent through the upper layers (HNSW's layer search with a result
+    list of one).  From the smallest id among the nodes of the highest
+    level, in each layer from the top down to 1, move to the neighbour of
+    smallest (d, id) key while that key is below the current node's, then
+    keep the node for the layer below.  ``upper`` holds one row per (node,
+    layer), node-major with ascending layers; a node's rows start at the sum
+    of the levels of the nodes before it.
+
+    Neighbours evaluated before are evaluated again: every one of them has a
+    key above the current node's (the current node is the best seen), so
+    this changes only the count, not the node reached.  Returns (node,
+    distance evaluations including the top entry's)."""
+    levels = np.asarray(levels, dtype=np.int64)
+    first_row = np.concatenate([[0], np.cumsum(levels)[:-1]])
+    top_level = int(levels.max())
+    cur = int(np.flatnonzero(levels == top_level)[0])
+    key = (float(dist(q, data[cur], metric)[()]), cur)
+    calls = 1
+    for layer in range(top_level, 0, -1):
+        while True:
+            nb = upper[first_row[cur] + layer - 1]
+            nb = nb[nb >= 0]
+            if nb.size == 0:
+                break
+            d = dist(q, data[nb], metric)
+            calls += nb.size
+            best = min((float(dv), int(i)) for dv, i in zip(d, nb))
+            if not best < key:
+                break
+            key = best
+            cur = best[1]
+    return cur, calls
+
+
+def hierarchy_entries(queries, data, levels, upper, metric: str = "l2"):
+    """``descend`` for each query: (entries int64 [nq], calls int64 [nq])."""
+    qs = np.atleast_2d(queries)
+    out = np.array([descend(q, data, levels, upper, metric) for q in qs], dtype=np.int64)
+    return out[:, 0], out[:, 1]
 
 
 def search_batch(data, graph, queries, entries, ef, k, **kw):

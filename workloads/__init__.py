@@ -2,7 +2,8 @@
 
 This package holds only input construction: point sets drawn from seeded
 mixtures, and the proximity graph a search runs over (exact kNN, symmetrize,
-neighbour-selection pruning, reachability repair, entry choice).  It holds
+neighbour-selection pruning, reachability repair, entry choice, and the
+upper layers of an HNSW-style hierarchy).  It holds
 none of FINGER's arithmetic (no residual split, basis, distribution matching,
 estimate or search); both the oracle and the GPU path consume what it
 produces and neither is imported here.
@@ -22,4 +23,6 @@ from .graph import (  # noqa: F401
     medoid,
     build_graph,
     pick_pivots,
+    draw_levels,
+    build_hierarchy,
 )

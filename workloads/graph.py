@@ -236,3 +236,46 @@ def build_graph(data: np.ndarray, knn_k: int = 16, max_degree: int = 32,
         "entry": int(entry),
     }
     return G, int(entry), stats
+
+
+def draw_levels(n: int, M: int, seed: int) -> np.ndarray:
+    """Top layer of each node as HNSW draws it: floor(-ln(U) / ln(M)) with U
+    uniform on (0, 1] from a seeded generator (int32 [n])."""
+    rng = np.random.default_rng(seed ^ 0x1E7E15)
+    u = 1.0 - rng.random(n)                       # (0, 1]
+    return np.floor(-np.log(u) / np.log(M)).astype(np.int32)
+
+
+def build_hierarchy(data: np.ndarray, levels: np.ndarray, M: int = 16, device="cpu"):
+    """Upper layers of an HNSW-style hierarchy over ``data`` (layer 0 is the
+    flat graph built elsewhere).
+
+    Layer l >= 1 holds the nodes with levels >= l.  HNSW builds its layers by
+    inserting nodes one at a time; this stand-in gives each layer the same
+    recipe as the flat graph instead (exact kNN with k = M / 2 inside the
+    layer, symmetrization, the neighbour-selection heuristic down to M, and
+    reachability repair from the layer's copy of the top entry).  The top
+    entry is the smallest id among the nodes of the highest level.
+
+    Returns (upper int32 [rows][M], top entry): node-major rows, one per
+    (node, layer) with 1 <= layer <= levels[node], ascending node id then
+    ascending layer, each holding global neighbour ids padded with -1."""
+    levels = np.asarray(levels, dtype=np.int64)
+    n = data.shape[0]
+    top_level = int(levels.max()) if n else 0
+    top = int(np.flatnonzero(levels == top_level)[0]) if n else -1
+    row0 = np.concatenate([[0], np.cumsum(levels)[:-1]]).astype(np.int64)
+    upper = np.full((int(levels.sum()), M), -1, dtype=np.int32)
+    for layer in range(1, top_level + 1):
+        S = np.flatnonzero(levels >= layer)
+        if S.size < 2:
+            continue
+        sub = np.ascontiguousarray(data[S])
+        k = max(1, min(M // 2, S.size - 1))
+        ids, d2 = knn_lists(sub, k, device=device)
+        indptr, nbr, dist = symmetrize(ids, d2)
+        G = prune_heuristic(sub, indptr, nbr, dist, M, device=device)
+        G, _, _ = repair_reachability(sub, G, int(np.searchsorted(S, top)), device=device)
+        rows = row0[S] + layer - 1
+        upper[rows] = np.where(G >= 0, S[np.maximum(G, 0)], -1)
+    return upper, top
