@@ -93,6 +93,11 @@ enum {
   FINGER_NCOUNTERS = 7
 };
 
+/* Start-point selectors for finger_search_params.entry (values >= 0 name a
+ * node). */
+#define FINGER_ENTRY_PIVOT (-1)
+#define FINGER_ENTRY_DESCENT (-2)
+
 /* ---------------------------------------------------------------- build */
 
 typedef struct finger_build_params {
@@ -174,6 +179,9 @@ typedef struct finger_tables_info {
   double corr_xy;           /* Pearson correlation of the sampled X (true residual
                                cosines) and Y (low-rank ones): Supplementary E's
                                rank rule grows r until it reaches 0.7 */
+  int32_t hierarchy_top_level; /* highest upper layer attached (0: none) */
+  int32_t hierarchy_top;       /* node the descent starts at (-1: none) */
+  int64_t hierarchy_rows;      /* upper-layer rows attached */
 } finger_tables_info;
 
 FINGER_API int finger_tables_info_get(const finger_tables* t, finger_tables_info* info /* host */);
@@ -211,7 +219,10 @@ typedef struct finger_search_params {
   int32_t ef;            /* efs for every query (ignored with ef_per_query);
                             the search keeps ef_eff = max(ef, K) entries */
   int32_t entry;         /* >= 0: start point p of every query (Algorithm 1);
-                            -1: each query starts at its nearest pivot */
+                            FINGER_ENTRY_PIVOT (-1): each query starts at its
+                            nearest pivot; FINGER_ENTRY_DESCENT (-2): where the
+                            descent through the attached upper layers ends
+                            (finger_hierarchy_attach, finger_descend) */
   int32_t warmup;        /* W: screening starts once more than W nodes have
                             been expanded (Algorithm 4's "> 5 updates"); < 0 = 5 */
   int32_t k_max;         /* row stride of out_ids/out_dist; >= every K */
@@ -273,7 +284,7 @@ FINGER_API int finger_search_workspace_size(const finger_tables* t, int64_t nq,
  * Returned distances are always exact (Supplementary G).
  *
  * Errors: EINVAL (nq < 0, k < 1 or k > n, ef < 1, entry out of range,
- * entry = -1 without pivots, FINGER/GATED mode on a rank-0 handle, GATED
+ * entry = -1 without pivots, entry = -2 without upper layers, FINGER/GATED mode on a rank-0 handle, GATED
  * without a gate, workspace too small or misaligned, ef_max > 1024, NULL
  * pointers), EOVERFLOW (ef_max or visited_capacity beyond the LDS budget),
  * EDEVICE.
@@ -282,6 +293,53 @@ FINGER_API int finger_search(const finger_tables* t, const float* queries, int64
                   const finger_search_params* p /* host */,
                   int32_t* out_ids, float* out_dist, int32_t* out_counters,
                   void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------ hierarchy */
+
+/*
+ * finger_hierarchy_attach - give the handle the upper layers of an HNSW-style
+ * hierarchical graph; the handle's graph is its layer 0.  The paper runs
+ * FINGER on HNSW graphs (Sections 1 and 4), where the start point p of
+ * Algorithm 1 is where a greedy descent through these layers ends
+ * (finger_descend; search with entry = FINGER_ENTRY_DESCENT).
+ *
+ *   levels [n] int32 (device): the highest layer of each node, 0..64.
+ *   upper  [rows][width] int32 (device): one row per (node, layer) with
+ *          1 <= layer <= levels[node], ordered by node id and then layer
+ *          (a node's rows start at the sum of the levels of the nodes before
+ *          it); a row lists the node's neighbours in that layer (ids of nodes
+ *          whose level is at least that layer, never the node itself), padded
+ *          with -1.  rows = sum of levels; 1 <= width <= 64.
+ *
+ * The descent starts at the smallest id among the nodes of the highest
+ * level.  Both arrays are copied (checked on the host); a later attach
+ * replaces the earlier one.  Synchronous.
+ * Errors: EINVAL (NULL handle or levels, upper NULL with rows > 0, width out
+ * of range, a level out of range, rows not the sum of the levels, a
+ * neighbour out of range, equal to its node or below the row's layer),
+ * EOVERFLOW (rows >= 2^31), ENOMEM, EDEVICE.
+ */
+FINGER_API int finger_hierarchy_attach(finger_tables* t, const int32_t* levels,
+                                       const int32_t* upper, int64_t rows, int32_t width);
+
+/*
+ * finger_descend - start points from the attached upper layers.  For each
+ * query, from the top node, in each layer from the highest down to 1: move
+ * to the listed neighbour of smallest (d, id) key while that key is below
+ * the current node's key, then keep the node for the layer below (HNSW's
+ * layer search with a result list of one).  d is the handle's distance
+ * (squared L2, or -q.x for FINGER_IP; queries are unit-normalized first for
+ * FINGER_ANGULAR).  Async.
+ *   queries     [nq][m] float (device, 16-byte aligned).
+ *   out_entries [nq] int32: the layer-0 start point of each query.
+ *   out_calls   [nq] int32 or NULL: distance evaluations, the top node's
+ *               included; a neighbour met again at a later hop is counted
+ *               again.
+ * Errors: EINVAL (NULL handle, no upper layers attached, nq < 0, NULL or
+ * misaligned pointers with nq > 0), ENOMEM, EDEVICE.
+ */
+FINGER_API int finger_descend(const finger_tables* t, const float* queries, int64_t nq,
+                              int32_t* out_entries, int32_t* out_calls, void* stream);
 
 /*
  * finger_estimate_edges - evaluate the search kernel's estimate for given

@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENODEV"
                 -5: "EOVERFLOW", -6: "EINTERNAL"}
 
 L2, ANGULAR, IP = 0, 1, 2
+ENTRY_PIVOT, ENTRY_DESCENT = -1, -2
 CODE_F32, CODE_BF16, CODE_FP8E4M3 = 0, 1, 2
 MODE_PLAIN, MODE_FINGER, MODE_GATED = 0, 1, 2
 SIGMA_STD, SIGMA_VARIANCE = 0, 1
@@ -35,6 +36,7 @@ EXPORTED = (
     "finger_exact_knn_workspace_size", "finger_exact_knn", "finger_gate_attach",
     "finger_gate_param_count", "finger_mlp_forward", "finger_mlp_backward",
     "finger_adam_step", "finger_gate_targets", "finger_last_error",
+    "finger_hierarchy_attach", "finger_descend",
 )
 
 
@@ -68,6 +70,8 @@ class TablesInfo(C.Structure):
         ("mu_hat", C.c_double), ("sigma_hat", C.c_double), ("eps", C.c_double),
         ("eps_gate", C.c_double), ("gate_attached", C.c_int32),
         ("edge_table_bytes", C.c_int64), ("corr_xy", C.c_double),
+        ("hierarchy_top_level", C.c_int32), ("hierarchy_top", C.c_int32),
+        ("hierarchy_rows", C.c_int64),
     ]
 
 
@@ -121,6 +125,10 @@ def load() -> C.CDLL:
     lib.finger_adam_step.restype = C.c_int
     lib.finger_adam_step.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
                                      C.c_float, i32, vp]
+    lib.finger_hierarchy_attach.restype = C.c_int
+    lib.finger_hierarchy_attach.argtypes = [vp, vp, vp, i64, i32]
+    lib.finger_descend.restype = C.c_int
+    lib.finger_descend.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.finger_gate_targets.restype = C.c_int
     lib.finger_gate_targets.argtypes = [vp, vp, i64, i32, vp, vp]
     _lib = lib

@@ -194,6 +194,30 @@ def finger_search(tables: Tables, queries: torch.Tensor, p: L.SearchParams | Non
     return ids, dist, ctr
 
 
+def finger_hierarchy_attach(tables: Tables, levels, upper) -> None:
+    """Attach the upper layers of an HNSW-style hierarchy (levels [n],
+    node-major rows upper [rows][width]); searches may then use
+    entry=L.ENTRY_DESCENT."""
+    lv = _dev_i32(levels)
+    up = _dev_i32(upper)
+    if up.dim() != 2:
+        raise ValueError("upper must be [rows][width]")
+    L.check(L.load().finger_hierarchy_attach(tables.handle, lv.data_ptr(), up.data_ptr(),
+                                             up.shape[0], up.shape[1]))
+
+
+def finger_descend(tables: Tables, queries: torch.Tensor, calls: bool = True):
+    """Start point of each query from the attached upper layers:
+    (entries int32 [nq], distance evaluations int32 [nq] or None)."""
+    queries = _dev_f32(queries)
+    nq = queries.shape[0]
+    ent = torch.empty(nq, dtype=torch.int32, device=queries.device)
+    cnt = torch.empty(nq, dtype=torch.int32, device=queries.device) if calls else None
+    L.check(L.load().finger_descend(tables.handle, queries.data_ptr(), nq, ent.data_ptr(),
+                                    cnt.data_ptr() if cnt is not None else None, _stream()))
+    return ent, cnt
+
+
 def finger_estimate_edges(tables: Tables, queries: torch.Tensor, q_index, centers, slots):
     lib = L.load()
     queries = _dev_f32(queries)

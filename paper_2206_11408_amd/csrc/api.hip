@@ -101,7 +101,7 @@ void free_tables(Tables* t) {
   if (t == nullptr) return;
   void* dev_ptrs[] = {t->data_owned, t->P, t->cc, t->pc, t->alpha, t->rho, t->codes, t->scale,
                       t->piv_ids, t->qprep_B, t->qprep_Bnorm, t->piv_b16, t->piv_norm, t->samples, t->xy, t->gate_w,
-                      t->gate_b};
+                      t->gate_b, t->h_row0, t->h_upper};
   for (void* p : dev_ptrs)
     if (p) (void)hipFree(p);
   std::free(t->P64_host);
@@ -395,6 +395,9 @@ int finger_tables_info_get(const finger_tables* th, finger_tables_info* info) {
   info->gate_attached = t->gate;
   info->edge_table_bytes = t->r > 0 ? (int64_t)(t->code_bytes + (size_t)t->n * t->deg * 8) : 0;
   info->corr_xy = t->corr_xy;
+  info->hierarchy_top_level = t->h_top >= 0 ? t->h_top_level : 0;
+  info->hierarchy_top = t->h_top;
+  info->hierarchy_rows = t->h_rows;
   return ok();
 }
 
@@ -471,8 +474,12 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   if (p->ef_per_query == nullptr && p->ef < 1) return fail(FINGER_EINVAL, "ef = %d < 1", p->ef);
   const int kmax_needed = p->k_per_query == nullptr ? p->k : 1;
   if (p->k_max < kmax_needed) return fail(FINGER_EINVAL, "k_max = %d < k = %d", p->k_max, p->k);
-  if (p->entry < -1 || p->entry >= t->n) return fail(FINGER_EINVAL, "entry = %d out of range", p->entry);
-  if (p->entry == -1 && t->npiv == 0) return fail(FINGER_EINVAL, "entry = -1 needs pivots in the tables");
+  if (p->entry < FINGER_ENTRY_DESCENT || p->entry >= t->n)
+    return fail(FINGER_EINVAL, "entry = %d out of range", p->entry);
+  if (p->entry == FINGER_ENTRY_PIVOT && t->npiv == 0)
+    return fail(FINGER_EINVAL, "entry = -1 needs pivots in the tables");
+  if (p->entry == FINGER_ENTRY_DESCENT && t->h_top < 0)
+    return fail(FINGER_EINVAL, "entry = -2 needs upper layers (finger_hierarchy_attach)");
   int ef_max = p->ef_max;
   if (perq) {
     if (ef_max < 1) return fail(FINGER_EINVAL, "ef_max must be set with per-query k or ef");
@@ -569,12 +576,14 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
     HIPCHK(launch_normalize_rows(queries, nq, t->m, qn, s));
     queries = qn;
   }
-  HIPCHK(hipMemsetAsync(queue, 0, 4, s));
-  HIPCHK(hipMemsetAsync(spill, 0xFF, (size_t)pl.waves * pl.spill_slots * 4, s));
-  const bool need_prep = p->mode != FINGER_MODE_PLAIN || p->entry == -1;
+  // fill kernels rather than memsets: a caller may capture this call in a graph
+  HIPCHK(launch_fill_u32(queue, 0u, 1, s));
+  HIPCHK(launch_fill_u32(spill, 0xFFFFFFFFu, (size_t)pl.waves * pl.spill_slots, s));
+  const bool need_prep = p->mode != FINGER_MODE_PLAIN || p->entry == FINGER_ENTRY_PIVOT;
   if (need_prep)
-    HIPCHK(launch_query_prep(*t, queries, nq, qq, pq, p->entry == -1 ? ent : nullptr, qscr, s,
-                             p->mode != FINGER_MODE_PLAIN));
+    HIPCHK(launch_query_prep(*t, queries, nq, qq, pq, p->entry == FINGER_ENTRY_PIVOT ? ent : nullptr,
+                             qscr, s, p->mode != FINGER_MODE_PLAIN));
+  if (p->entry == FINGER_ENTRY_DESCENT) HIPCHK(launch_descend(*t, queries, nq, ent, nullptr, s));
   SearchLaunch L{};
   L.queries = queries;
   L.nq = nq;
@@ -589,7 +598,7 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.efq = p->ef_per_query;
   L.qq = qq;
   L.pq = pq;
-  L.entries = p->entry == -1 ? ent : nullptr;
+  L.entries = p->entry < 0 ? ent : nullptr;
   L.out_ids = out_ids;
   L.out_dist = out_dist;
   L.counters = out_counters;
@@ -609,6 +618,95 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   if (ev0) HIPCHK(hipEventRecord(ev0, s));
   HIPCHK(launch_search(*t, L, s));
   if (ev1) HIPCHK(hipEventRecord(ev1, s));
+  return ok();
+}
+
+int finger_hierarchy_attach(finger_tables* th, const int32_t* levels, const int32_t* upper,
+                            int64_t rows, int32_t width) {
+  using namespace finger;
+  if (th == nullptr || levels == nullptr) return fail(FINGER_EINVAL, "NULL handle or levels");
+  if (rows < 0) return fail(FINGER_EINVAL, "rows = %lld < 0", (long long)rows);
+  if (rows > 0 && upper == nullptr) return fail(FINGER_EINVAL, "upper is NULL with rows > 0");
+  if (width < 1 || width > kMaxDegree) return fail(FINGER_EINVAL, "width = %d out of range [1, %d]", width, kMaxDegree);
+  if (rows >= (int64_t(1) << 31)) return fail(FINGER_EOVERFLOW, "rows = %lld >= 2^31", (long long)rows);
+  Tables* t = reinterpret_cast<Tables*>(th);
+  const int64_t n = t->n;
+  std::vector<int32_t> lv, up, row0;
+  try {
+    lv.resize((size_t)n);
+    up.resize((size_t)rows * width);
+    row0.resize((size_t)n);
+  } catch (const std::bad_alloc&) {
+    return fail(FINGER_ENOMEM, "host copy of the hierarchy (%lld rows)", (long long)rows);
+  }
+  HIPCHK(hipMemcpy(lv.data(), levels, (size_t)n * 4, hipMemcpyDeviceToHost));
+  if (rows > 0) HIPCHK(hipMemcpy(up.data(), upper, up.size() * 4, hipMemcpyDeviceToHost));
+  int64_t sum = 0;
+  int top_level = 0, top = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (lv[i] < 0 || lv[i] > 64) return fail(FINGER_EINVAL, "levels[%lld] = %d out of range [0, 64]", (long long)i, lv[i]);
+    row0[i] = lv[i] > 0 ? (int32_t)sum : -1;
+    sum += lv[i];
+    if (lv[i] > top_level) { top_level = lv[i]; top = (int)i; }
+  }
+  if (sum != rows) return fail(FINGER_EINVAL, "rows = %lld but the levels sum to %lld", (long long)rows, (long long)sum);
+  for (int64_t i = 0; i < n; ++i)
+    for (int l = 1; l <= lv[i]; ++l) {
+      const int32_t* r = up.data() + (size_t)(row0[i] + l - 1) * width;
+      for (int j = 0; j < width; ++j) {
+        const int32_t v = r[j];
+        if (v == -1) continue;
+        if (v < -1 || v >= n || v == i || lv[v] < l)
+          return fail(FINGER_EINVAL, "node %lld layer %d: neighbour %d is out of range, the node itself or not in the layer",
+                      (long long)i, l, v);
+      }
+    }
+  int32_t *d_row0 = nullptr, *d_up = nullptr;
+  int st = dev_alloc(reinterpret_cast<void**>(&d_row0), (size_t)n * 4, "hierarchy row offsets");
+  if (st != FINGER_OK) return st;
+  if ((st = dev_alloc(reinterpret_cast<void**>(&d_up), std::max<size_t>(up.size() * 4, 4), "hierarchy rows")) != FINGER_OK) {
+    (void)hipFree(d_row0);
+    return st;
+  }
+  hipError_t e = hipMemcpy(d_row0, row0.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && rows > 0) e = hipMemcpy(d_up, up.data(), up.size() * 4, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d_row0);
+    (void)hipFree(d_up);
+    return fail(FINGER_EDEVICE, "copying the hierarchy: %s", hipGetErrorString(e));
+  }
+  if (t->h_row0) (void)hipFree(t->h_row0);
+  if (t->h_upper) (void)hipFree(t->h_upper);
+  t->h_row0 = d_row0;
+  t->h_upper = d_up;
+  t->h_rows = rows;
+  t->h_width = width;
+  t->h_top_level = top_level;
+  t->h_top = top;
+  return ok();
+}
+
+int finger_descend(const finger_tables* th, const float* queries, int64_t nq, int32_t* out_entries,
+                   int32_t* out_calls, void* stream) {
+  using namespace finger;
+  if (th == nullptr) return fail(FINGER_EINVAL, "NULL handle");
+  const Tables* t = reinterpret_cast<const Tables*>(th);
+  if (t->h_top < 0) return fail(FINGER_EINVAL, "no upper layers attached (finger_hierarchy_attach)");
+  if (nq < 0) return fail(FINGER_EINVAL, "nq < 0");
+  if (nq == 0) return ok();
+  if (queries == nullptr || out_entries == nullptr) return fail(FINGER_EINVAL, "NULL pointer");
+  if ((reinterpret_cast<uintptr_t>(queries) & 15u) != 0) return fail(FINGER_EINVAL, "queries must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (t->metric == FINGER_ANGULAR) {
+    DevBuf<float> qn;
+    int st = dev_alloc(reinterpret_cast<void**>(&qn.p), (size_t)nq * t->m * 4, "normalized queries");
+    if (st != FINGER_OK) return st;
+    HIPCHK(launch_normalize_rows(queries, nq, t->m, qn.p, s));
+    HIPCHK(launch_descend(*t, qn.p, nq, out_entries, out_calls, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ok();
+  }
+  HIPCHK(launch_descend(*t, queries, nq, out_entries, out_calls, s));
   return ok();
 }
 

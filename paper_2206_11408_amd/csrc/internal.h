@@ -84,6 +84,13 @@ struct Tables {
   double eps_gate = 0;
   uint16_t* gate_w = nullptr;      // bf16 weights packed as GateLayout
   float* gate_b = nullptr;         // float biases b1 [hp], b2 [hp], b3 [1]
+  // upper layers of an HNSW-style hierarchy (finger_hierarchy_attach)
+  int32_t h_top = -1;              // descent start: smallest id of the top level
+  int32_t h_top_level = 0;
+  int32_t h_width = 0;
+  int64_t h_rows = 0;
+  int32_t* h_row0 = nullptr;       // [n] first upper row of each node (-1: level 0)
+  int32_t* h_upper = nullptr;      // [h_rows][h_width]
 };
 
 // ------------------------------------------------------------ launchers
@@ -94,6 +101,14 @@ struct Tables {
 enum GemmEpi { GEMM_STORE = 0 };
 hipError_t launch_gemm_nt(const float* A, int64_t rows, const float* B, int64_t cols, int K,
                           float* C, int64_t ldc, hipStream_t s);
+
+// greedy descent through the attached upper layers: out[i] = layer-0 start
+// point of query i, calls[i] (may be NULL) = distance evaluations
+hipError_t launch_descend(const Tables& t, const float* Q, int64_t nq, int32_t* out, int32_t* calls,
+                          hipStream_t s);
+
+// p[0..count) = value (a kernel, so that callers may capture it in a graph)
+hipError_t launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s);
 
 // query preparation: qq[i] = |q_i|^2, Pq[i][0..r) = P q_i, and (if npiv > 0)
 // entries[i] = nearest pivot id by exact squared distance

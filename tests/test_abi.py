@@ -48,7 +48,8 @@ int main(void) {
   P(finger_search_params, k_per_query); P(finger_search_params, ef_max);
   P(finger_search_params, log_features); P(finger_search_params, log_count);
   P(finger_tables_info, n_samples_used); P(finger_tables_info, mu); P(finger_tables_info, gate_attached);
-  P(finger_tables_info, edge_table_bytes);
+  P(finger_tables_info, edge_table_bytes); P(finger_tables_info, corr_xy);
+  P(finger_tables_info, hierarchy_top); P(finger_tables_info, hierarchy_rows);
   return 0;
 }
 """
@@ -164,6 +165,8 @@ def test_null_handle_search_calls():
     assert lib.finger_search(None, None, 0, C.byref(sp), None, None, None, None, 0, None) == L.FINGER_EINVAL
     info = L.TablesInfo()
     assert lib.finger_tables_info_get(None, C.byref(info)) == L.FINGER_EINVAL
+    assert lib.finger_hierarchy_attach(None, 1 << 20, 1 << 20, 4, 16) == L.FINGER_EINVAL
+    assert lib.finger_descend(None, 1 << 20, 4, 1 << 20, None, None) == L.FINGER_EINVAL
     lib.finger_free_tables(None)  # no-op
 
 
