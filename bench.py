@@ -103,6 +103,9 @@ def main() -> int:
                          "and without distribution matching) and the rank rule")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="time the default launch geometry instead of the autotuned one")
+    ap.add_argument("--hierarchy", action="store_true",
+                    help="also build HNSW-style upper layers (M = 16) and report both modes "
+                         "started from the descent instead of the nearest pivot")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (the reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -171,20 +174,20 @@ def main() -> int:
 
     launch = {}   # (mode, code) -> tuned launch settings
 
-    def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0):
-        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1, code_prefetch=prefetch)
+    def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0, entry=L.ENTRY_PIVOT):
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, code_prefetch=prefetch)
         if time_kernel:
             p.kernel_events[0] = kev[0].cuda_event
             p.kernel_events[1] = kev[1].cuda_event
         return api.finger_search(tab, d_q, p, out=out)
 
-    def sweep(tab, mode, prefetch=0):
+    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT):
         res = []
         for ef in EF_SWEEP:
-            run(tab, mode, ef, prefetch=prefetch)
+            run(tab, mode, ef, prefetch=prefetch, entry=entry)
             torch.cuda.synchronize()
             ev[0].record()
-            ids, dist, ctr = run(tab, mode, ef, prefetch=prefetch)
+            ids, dist, ctr = run(tab, mode, ef, prefetch=prefetch, entry=entry)
             ev[1].record()
             torch.cuda.synchronize()
             ms = ev[0].elapsed_time(ev[1])
@@ -202,23 +205,23 @@ def main() -> int:
         ok = [r for r in res if r["recall"] >= TARGET_RECALL]
         return res, (min(ok, key=lambda r: r["ef"]) if ok else max(res, key=lambda r: r["recall"]))
 
-    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0):
+    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0, entry=L.ENTRY_PIVOT):
         nq = a.nq
         out = (torch.empty((nq, 10), dtype=torch.int32, device=dev),
                torch.empty((nq, 10), dtype=torch.float32, device=dev),
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
         if a.tune:
-            base = dict(mode=mode, k=10, ef=ef, entry=-1)
+            base = dict(mode=mode, k=10, ef=ef, entry=entry)
             ch = tune.autotune(tab, d_q, base, repeats=3, cache_path=None, log=log)
             if prefetch != 0:   # an explicitly requested code-prefetch setting stays fixed
                 best = min((t, c) for t, c in ch["all"] if c["code_prefetch"] == prefetch)[1]
                 ch = dict(best)
-            launch[(mode, id(tab), prefetch)] = {k: ch[k] for k in
-                                                 ("waves_per_cu", "persistent", "code_prefetch",
-                                                  "visited_capacity")}
-            log(f"tuned launch mode={mode}: {launch[(mode, id(tab), prefetch)]}")
-        geo = launch.get((mode, id(tab), prefetch), {})
-        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1,
+            launch[(mode, id(tab), prefetch, entry)] = {k: ch[k] for k in
+                                                        ("waves_per_cu", "persistent", "code_prefetch",
+                                                         "visited_capacity")}
+            log(f"tuned launch mode={mode}: {launch[(mode, id(tab), prefetch, entry)]}")
+        geo = launch.get((mode, id(tab), prefetch, entry), {})
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry,
                               code_prefetch=geo.get("code_prefetch", prefetch),
                               waves_per_cu=geo.get("waves_per_cu", 0),
                               persistent=geo.get("persistent", 0),
@@ -296,6 +299,36 @@ def main() -> int:
                               launch=tx["launch"],
                               speedup_vs_plain=round(tx["qps"] / tp["qps"], 4))
         log(f"finger {variant} timed: {tx}")
+
+    hier = None
+    if a.hierarchy:
+        from workloads import build_hierarchy, draw_levels
+        t0 = time.time()
+        levels = draw_levels(a.n, 16, spec.seed)
+        upper, top = build_hierarchy(data, levels, M=16, device="cuda")
+        api.finger_hierarchy_attach(tabF, levels, upper)
+        log(f"hierarchy M=16 in {time.time() - t0:.1f}s: top level {levels.max()}, "
+            f"{upper.shape[0]} upper rows, top node {top}")
+        api.finger_descend(tabF, d_q)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(a.steps):
+            dent, dcalls = api.finger_descend(tabF, d_q)
+        ev[1].record()
+        torch.cuda.synchronize()
+        d_ms = ev[0].elapsed_time(ev[1]) / a.steps
+        hier = {"levels": int(levels.max()), "upper_rows": int(upper.shape[0]),
+                "descent_ms": round(d_ms, 4), "descent_calls": round(float(dcalls.float().mean()), 1)}
+        for nm, mode in (("plain", L.MODE_PLAIN), ("finger", L.MODE_FINGER)):
+            log(f"sweep {nm} from descent entries")
+            sw, op = sweep(tabF, mode, entry=L.ENTRY_DESCENT)
+            th = timed(tabF, mode, op["ef"], a.steps, a.warmup, cb, fp8, entry=L.ENTRY_DESCENT)
+            log(f"{nm} timed from descent entries: {th}")
+            hier[nm] = dict(ef=op["ef"], recall=round(th["recall"], 4), qps=round(th["qps"], 1),
+                            kernel_ms=round(th["kernel_ms"], 4), exact=round(th["exact"], 1),
+                            launch=th["launch"])
+        hier["speedup_vs_plain"] = round(hier["finger"]["qps"] / hier["plain"]["qps"], 4)
+        hier["pivot_entries"] = dict(plain_exact=round(tp["exact"], 1), finger_exact=round(tf["exact"], 1))
 
     gated = None
     if a.gate > 0:
@@ -406,6 +439,8 @@ def main() -> int:
         line["gated"] = gated
     if ablation_out:
         line["ablation"] = ablation_out
+    if hier:
+        line["descent_entries"] = hier
     print(json.dumps(line), flush=True)
     return 0
 

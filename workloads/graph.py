@@ -246,16 +246,22 @@ def draw_levels(n: int, M: int, seed: int) -> np.ndarray:
     return np.floor(-np.log(u) / np.log(M)).astype(np.int32)
 
 
-def build_hierarchy(data: np.ndarray, levels: np.ndarray, M: int = 16, device="cpu"):
+def build_hierarchy(data: np.ndarray, levels: np.ndarray, M: int = 16, candidates: int = 128,
+                    device="cpu"):
     """Upper layers of an HNSW-style hierarchy over ``data`` (layer 0 is the
     flat graph built elsewhere).
 
     Layer l >= 1 holds the nodes with levels >= l.  HNSW builds its layers by
-    inserting nodes one at a time; this stand-in gives each layer the same
-    recipe as the flat graph instead (exact kNN with k = M / 2 inside the
-    layer, symmetrization, the neighbour-selection heuristic down to M, and
-    reachability repair from the layer's copy of the top entry).  The top
-    entry is the smallest id among the nodes of the highest level.
+    inserting nodes one at a time, linking each to M of the ``candidates``
+    nearest it finds in the layer (its construction beam) through the
+    neighbour-selection heuristic, and adding the reverse links (re-pruned by
+    the heuristic when a row overflows).  This stand-in takes the end state
+    directly: exact kNN with k = ``candidates`` inside the layer,
+    symmetrization, the heuristic down to M, and reachability repair from the
+    layer's copy of the top entry.  A wide candidate pool matters on
+    clustered data: with only the few nearest, the heuristic has no
+    neighbour outside the node's own cluster to keep.  The top entry is the
+    smallest id among the nodes of the highest level.
 
     Returns (upper int32 [rows][M], top entry): node-major rows, one per
     (node, layer) with 1 <= layer <= levels[node], ascending node id then
@@ -271,7 +277,7 @@ def build_hierarchy(data: np.ndarray, levels: np.ndarray, M: int = 16, device="c
         if S.size < 2:
             continue
         sub = np.ascontiguousarray(data[S])
-        k = max(1, min(M // 2, S.size - 1))
+        k = max(1, min(candidates, S.size - 1))
         ids, d2 = knn_lists(sub, k, device=device)
         indptr, nbr, dist = symmetrize(ids, d2)
         G = prune_heuristic(sub, indptr, nbr, dist, M, device=device)
