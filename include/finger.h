@@ -294,6 +294,52 @@ FINGER_API int finger_search(const finger_tables* t, const float* queries, int64
                   int32_t* out_ids, float* out_dist, int32_t* out_counters,
                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------- graph */
+
+typedef struct finger_graph_stats {
+  int64_t sym_edges;              /* directed edges after symmetrization */
+  int32_t sym_degree_max;         /* longest row before pruning */
+  int32_t components_before_repair; /* 1 + number of repair steps */
+  int64_t edges_added;            /* edges the repair appended */
+  double ms_knn, ms_symmetrize, ms_prune, ms_repair; /* wall time per phase */
+} finger_graph_stats;
+
+/*
+ * finger_build_graph - the flat proximity graph the search runs over, built
+ * on the GPU.  The paper takes the graph as given (Section 3.3 and
+ * Algorithm 2 start from G = (D, E); its experiments use HNSW graphs); this
+ * is the stand-in for HNSW's layer 0, in four steps:
+ *   1. the knn_k nearest other points of every point, by (d2, id);
+ *   2. symmetrization: every edge and its reverse, rows sorted by (d2, id),
+ *      no duplicates;
+ *   3. rows longer than max_degree: HNSW's neighbour-selection heuristic
+ *      (scan the row in order; keep a candidate iff fewer than max_degree
+ *      are kept and it is strictly closer to the base than to every kept
+ *      neighbour);
+ *   4. reachability repair from `entry`: while a node is unreached, the
+ *      smallest-id unreached node u gets an edge from the reached node with a
+ *      free slot of smallest (d2 to u, id), appended to that node's row; u
+ *      gets the reverse edge if it has a free slot and does not list the node
+ *      yet; everything reachable from u is then reached.
+ * Distances are float32 sums of squared differences (exact for integer data
+ * whose squared norms stay below 2^24); FINGER_ANGULAR builds the graph of
+ * the unit-normalized points.
+ *   data      [n][m] float (device, 16-byte aligned), m % 4 == 0.
+ *   out_graph [n][max_degree] int32 (device): rows of neighbour ids, -1
+ *             padded; repair edges follow the row's own entries.
+ *   stats     host, or NULL.
+ * Synchronous; allocates its scratch (about 2nk * 40 bytes plus the exact
+ * kNN's candidate lists) and frees it before returning.
+ * Errors: EINVAL (NULL pointers, n < 2, m, knn_k outside 1..min(n - 1, 127),
+ * max_degree outside 1..64, metric not L2/ANGULAR, entry out of range),
+ * EOVERFLOW (2 n knn_k >= 2^31, or no reached node has a free slot for a
+ * repair), ENOMEM, EDEVICE.
+ */
+FINGER_API int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k,
+                                  int32_t max_degree, int32_t metric, int32_t entry,
+                                  int32_t* out_graph, finger_graph_stats* stats /* host */,
+                                  void* stream);
+
 /* ------------------------------------------------------------ hierarchy */
 
 /*

@@ -36,7 +36,7 @@ EXPORTED = (
     "finger_exact_knn_workspace_size", "finger_exact_knn", "finger_gate_attach",
     "finger_gate_param_count", "finger_mlp_forward", "finger_mlp_backward",
     "finger_adam_step", "finger_gate_targets", "finger_last_error",
-    "finger_hierarchy_attach", "finger_descend",
+    "finger_hierarchy_attach", "finger_descend", "finger_build_graph",
 )
 
 
@@ -72,6 +72,15 @@ class TablesInfo(C.Structure):
         ("edge_table_bytes", C.c_int64), ("corr_xy", C.c_double),
         ("hierarchy_top_level", C.c_int32), ("hierarchy_top", C.c_int32),
         ("hierarchy_rows", C.c_int64),
+    ]
+
+
+class GraphStats(C.Structure):
+    _fields_ = [
+        ("sym_edges", C.c_int64), ("sym_degree_max", C.c_int32),
+        ("components_before_repair", C.c_int32), ("edges_added", C.c_int64),
+        ("ms_knn", C.c_double), ("ms_symmetrize", C.c_double), ("ms_prune", C.c_double),
+        ("ms_repair", C.c_double),
     ]
 
 
@@ -125,6 +134,8 @@ def load() -> C.CDLL:
     lib.finger_adam_step.restype = C.c_int
     lib.finger_adam_step.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
                                      C.c_float, i32, vp]
+    lib.finger_build_graph.restype = C.c_int
+    lib.finger_build_graph.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, P(GraphStats), vp]
     lib.finger_hierarchy_attach.restype = C.c_int
     lib.finger_hierarchy_attach.argtypes = [vp, vp, vp, i64, i32]
     lib.finger_descend.restype = C.c_int

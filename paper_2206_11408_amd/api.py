@@ -194,6 +194,19 @@ def finger_search(tables: Tables, queries: torch.Tensor, p: L.SearchParams | Non
     return ids, dist, ctr
 
 
+def finger_build_graph(data: torch.Tensor, knn_k: int = 16, max_degree: int = 32, entry: int = 0,
+                       metric: int = L.L2):
+    """The flat graph built on the GPU (finger_build_graph): returns
+    (graph int32 [n, max_degree] on the data's device, stats dict)."""
+    data = _dev_f32(data)
+    n, m = data.shape
+    G = torch.empty((n, max_degree), dtype=torch.int32, device=data.device)
+    st = L.GraphStats()
+    L.check(L.load().finger_build_graph(data.data_ptr(), n, m, knn_k, max_degree, metric, entry,
+                                        G.data_ptr(), C.byref(st), _stream()))
+    return G, {name: getattr(st, name) for name, _ in L.GraphStats._fields_}
+
+
 def finger_hierarchy_attach(tables: Tables, levels, upper) -> None:
     """Attach the upper layers of an HNSW-style hierarchy (levels [n],
     node-major rows upper [rows][width]); searches may then use

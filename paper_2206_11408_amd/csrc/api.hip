@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -117,9 +118,14 @@ struct Guard {  // frees a half-built handle on error paths
 template <typename T>
 struct DevBuf {  // scoped temporary device buffer
   T* p = nullptr;
-  ~DevBuf() {
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  void reset() {
     if (p) (void)hipFree(p);
+    p = nullptr;
   }
+  ~DevBuf() { reset(); }
 };
 
 }  // namespace
@@ -618,6 +624,220 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   if (ev0) HIPCHK(hipEventRecord(ev0, s));
   HIPCHK(launch_search(*t, L, s));
   if (ev1) HIPCHK(hipEventRecord(ev1, s));
+  return ok();
+}
+
+int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, int32_t max_degree,
+                       int32_t metric, int32_t entry, int32_t* out_graph, finger_graph_stats* stats,
+                       void* stream) {
+  using namespace finger;
+  if (data == nullptr || out_graph == nullptr) return fail(FINGER_EINVAL, "NULL data or out_graph");
+  if (n < 2) return fail(FINGER_EINVAL, "n = %lld < 2", (long long)n);
+  if (m <= 0 || m > kMaxDim || m % 4 != 0) return fail(FINGER_EINVAL, "m = %d must be a multiple of 4 in [4, %d]", m, kMaxDim);
+  if (knn_k < 1 || knn_k > 127 || knn_k > n - 1)
+    return fail(FINGER_EINVAL, "knn_k = %d out of range [1, min(n - 1, 127)]", knn_k);
+  if (max_degree < 1 || max_degree > kMaxDegree)
+    return fail(FINGER_EINVAL, "max_degree = %d out of range [1, %d]", max_degree, kMaxDegree);
+  if (metric != FINGER_L2 && metric != FINGER_ANGULAR)
+    return fail(FINGER_EINVAL, "metric %d: the graph recipe needs L2 or angular distances", metric);
+  if (entry < 0 || entry >= n) return fail(FINGER_EINVAL, "entry = %d out of range", entry);
+  if ((reinterpret_cast<uintptr_t>(data) & 15u) != 0) return fail(FINGER_EINVAL, "data must be 16-byte aligned");
+  const int k = knn_k, k1 = knn_k + 1, W = max_degree;
+  const int64_t nk = n * k, ne = 2 * nk;
+  if (ne >= (int64_t(1) << 31)) return fail(FINGER_EOVERFLOW, "2 n knn_k = %lld >= 2^31", (long long)ne);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto ms_since = [&](std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(now() - t0).count();
+  };
+  finger_graph_stats st{};
+  int rc = FINGER_OK;
+  auto alloc = [&](auto& buf, size_t bytes, const char* what) {
+    if (rc == FINGER_OK) rc = dev_alloc(reinterpret_cast<void**>(&buf.p), std::max<size_t>(bytes, 4), what);
+  };
+
+  // 1. kNN (k + 1 with the point itself, which is then dropped)
+  auto t0 = now();
+  DevBuf<float> normed;
+  const float* X = data;
+  if (metric == FINGER_ANGULAR) {
+    alloc(normed, (size_t)n * m * 4, "normalized points");
+    if (rc != FINGER_OK) return rc;
+    HIPCHK(launch_normalize_rows(data, n, m, normed.p, s));
+    X = normed.p;
+  }
+  DevBuf<char> kws;
+  DevBuf<int32_t> ids1, ids;
+  DevBuf<float> d1, dk;
+  alloc(kws, exact_knn_ws_bytes(n, m, n, k1), "kNN workspace");
+  alloc(ids1, (size_t)n * k1 * 4, "kNN ids");
+  alloc(d1, (size_t)n * k1 * 4, "kNN distances");
+  alloc(ids, (size_t)nk * 4, "kNN lists");
+  alloc(dk, (size_t)nk * 4, "kNN list distances");
+  if (rc != FINGER_OK) return rc;
+  HIPCHK(launch_exact_knn(X, n, m, X, n, k1, FINGER_L2, ids1.p, d1.p, kws.p, s));
+  HIPCHK(launch_drop_self(ids1.p, d1.p, n, k1, k, ids.p, dk.p, s));
+  HIPCHK(hipStreamSynchronize(s));
+  st.ms_knn = ms_since(t0);
+  kws.reset();
+  ids1.reset();
+  d1.reset();
+
+  // 2. symmetrization: stable sorts by target, then by (source, distance)
+  t0 = now();
+  int nbits = 1;
+  while ((int64_t(1) << nbits) < n) ++nbits;
+  DevBuf<uint32_t> ka, kb, va, vb, cnt, indptr;
+  DevBuf<uint64_t> k2a, k2b;
+  DevBuf<char> tmp;
+  alloc(ka, (size_t)ne * 4, "edge keys");
+  alloc(kb, (size_t)ne * 4, "edge keys");
+  alloc(va, (size_t)ne * 4, "edge order");
+  alloc(vb, (size_t)ne * 4, "edge order");
+  alloc(k2a, (size_t)ne * 8, "edge keys");
+  alloc(k2b, (size_t)ne * 8, "edge keys");
+  alloc(cnt, (size_t)(n + 1) * 4, "row counts");
+  alloc(indptr, (size_t)(n + 1) * 4, "row offsets");
+  if (rc != FINGER_OK) return rc;
+  size_t tb1 = 0, tb2 = 0, tb3 = 0, tb4 = 0;
+  HIPCHK(radix_sort_u32(nullptr, tb1, ka.p, kb.p, va.p, vb.p, ne, nbits, s));
+  HIPCHK(radix_sort_u64(nullptr, tb2, k2a.p, k2b.p, vb.p, va.p, ne, 32 + nbits, s));
+  HIPCHK(exclusive_sum_u32(nullptr, tb3, ka.p, kb.p, ne, s));
+  HIPCHK(exclusive_sum_u32(nullptr, tb4, cnt.p, indptr.p, n + 1, s));
+  size_t tbytes = std::max(std::max(tb1, tb2), std::max(tb3, tb4));
+  alloc(tmp, tbytes, "sort scratch");
+  if (rc != FINGER_OK) return rc;
+  HIPCHK(launch_sym_keys_dst(n, k, ids.p, dk.p, ka.p, va.p, s));
+  size_t tb = tbytes;
+  HIPCHK(radix_sort_u32(tmp.p, tb, ka.p, kb.p, va.p, vb.p, ne, nbits, s));
+  HIPCHK(launch_sym_keys_src_d(n, k, ids.p, dk.p, vb.p, k2a.p, s));
+  tb = tbytes;
+  HIPCHK(radix_sort_u64(tmp.p, tb, k2a.p, k2b.p, vb.p, va.p, ne, 32 + nbits, s));
+  // va: edges by (source, distance, target); ka = keep flags, kb = kept rank
+  HIPCHK(launch_fill_u32(cnt.p, 0u, (size_t)(n + 1), s));
+  HIPCHK(launch_sym_dedupe(n, k, ids.p, dk.p, va.p, ka.p, cnt.p, s));
+  tb = tbytes;
+  HIPCHK(exclusive_sum_u32(tmp.p, tb, ka.p, kb.p, ne, s));
+  tb = tbytes;
+  HIPCHK(exclusive_sum_u32(tmp.p, tb, cnt.p, indptr.p, n + 1, s));
+  std::vector<uint32_t> ip_h;
+  try {
+    ip_h.resize((size_t)n + 1);
+  } catch (const std::bad_alloc&) {
+    return fail(FINGER_ENOMEM, "host row offsets");
+  }
+  HIPCHK(hipMemcpyAsync(ip_h.data(), indptr.p, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t total = ip_h[(size_t)n];
+  uint32_t dmax = 0;
+  for (int64_t i = 0; i < n; ++i) dmax = std::max(dmax, ip_h[(size_t)i + 1] - ip_h[(size_t)i]);
+  st.sym_edges = total;
+  st.sym_degree_max = (int32_t)dmax;
+  DevBuf<int32_t> nbr;
+  DevBuf<float> nd;
+  alloc(nbr, (size_t)total * 4, "symmetrized rows");
+  alloc(nd, (size_t)total * 4, "symmetrized distances");
+  if (rc != FINGER_OK) return rc;
+  HIPCHK(launch_sym_fill(n, k, ids.p, dk.p, va.p, ka.p, kb.p, nbr.p, nd.p, s));
+  HIPCHK(hipStreamSynchronize(s));
+  st.ms_symmetrize = ms_since(t0);
+
+  // 3. neighbour-selection heuristic on long rows
+  t0 = now();
+  HIPCHK(launch_prune(X, n, m, indptr.p, nbr.p, nd.p, W, out_graph, s));
+  HIPCHK(hipStreamSynchronize(s));
+  st.ms_prune = ms_since(t0);
+
+  // 4. reachability repair from the entry (host loop; each step depends on the last)
+  t0 = now();
+  DevBuf<int32_t> deg, fa, fb;
+  DevBuf<uint32_t> reached, ctr;
+  DevBuf<unsigned long long> best;
+  alloc(deg, (size_t)n * 4, "degrees");
+  alloc(fa, (size_t)n * 4, "BFS frontier");
+  alloc(fb, (size_t)n * 4, "BFS frontier");
+  alloc(reached, (size_t)n * 4, "reached flags");
+  alloc(ctr, 4, "BFS counter");
+  alloc(best, 8, "nearest key");
+  if (rc != FINGER_OK) return rc;
+  std::vector<int32_t> deg_h, row_h((size_t)W), next_h;
+  std::vector<uint8_t> reached_h;
+  try {
+    deg_h.resize((size_t)n);
+    reached_h.assign((size_t)n, 0);
+    next_h.resize((size_t)n);
+  } catch (const std::bad_alloc&) {
+    return fail(FINGER_ENOMEM, "host repair state");
+  }
+  HIPCHK(launch_degrees(out_graph, n, W, deg.p, s));
+  HIPCHK(launch_fill_u32(reached.p, 0u, (size_t)n, s));
+  HIPCHK(hipMemcpyAsync(deg_h.data(), deg.p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto put = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+  };
+  auto get = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+  };
+  const uint32_t one = 1u, zero = 0u;
+  auto mark_from = [&](int32_t start) -> hipError_t {
+    reached_h[(size_t)start] = 1;
+    hipError_t e = put(reached.p + start, &one, 4);
+    if (e == hipSuccess) e = put(fa.p, &start, 4);
+    int32_t* cur = fa.p;
+    int32_t* nxt = fb.p;
+    int64_t fsize = 1;
+    while (e == hipSuccess && fsize > 0) {
+      e = put(ctr.p, &zero, 4);
+      if (e == hipSuccess) e = launch_bfs_level(out_graph, W, cur, fsize, reached.p, nxt, ctr.p, s);
+      uint32_t got = 0;
+      if (e == hipSuccess) e = get(&got, ctr.p, 4);
+      if (e == hipSuccess && got > 0) e = get(next_h.data(), nxt, (size_t)got * 4);
+      for (uint32_t t = 0; e == hipSuccess && t < got; ++t) reached_h[(size_t)next_h[t]] = 1;
+      std::swap(cur, nxt);
+      fsize = got;
+    }
+    return e;
+  };
+  HIPCHK(mark_from(entry));
+  int64_t u = 0;
+  int repairs = 0;
+  int64_t added = 0;
+  while (true) {
+    while (u < n && reached_h[(size_t)u]) ++u;
+    if (u == n) break;
+    ++repairs;
+    const unsigned long long none = ~0ull;
+    HIPCHK(put(best.p, &none, 8));
+    HIPCHK(launch_nearest_free(X, n, m, (int)u, reached.p, deg.p, W, best.p, s));
+    unsigned long long bk = 0;
+    HIPCHK(get(&bk, best.p, 8));
+    if (bk == none) return fail(FINGER_EOVERFLOW, "repair of node %lld: no reached node has a free slot", (long long)u);
+    const int32_t v = (int32_t)(uint32_t)bk;
+    const int32_t uu = (int32_t)u;
+    HIPCHK(put(out_graph + (int64_t)v * W + deg_h[(size_t)v], &uu, 4));
+    ++deg_h[(size_t)v];
+    HIPCHK(put(deg.p + v, &deg_h[(size_t)v], 4));
+    ++added;
+    if (deg_h[(size_t)u] < W) {
+      HIPCHK(get(row_h.data(), out_graph + u * W, (size_t)W * 4));
+      bool has = false;
+      for (int t = 0; t < deg_h[(size_t)u]; ++t) has = has || row_h[(size_t)t] == v;
+      if (!has) {
+        HIPCHK(put(out_graph + u * W + deg_h[(size_t)u], &v, 4));
+        ++deg_h[(size_t)u];
+        HIPCHK(put(deg.p + u, &deg_h[(size_t)u], 4));
+        ++added;
+      }
+    }
+    HIPCHK(mark_from(uu));
+  }
+  st.components_before_repair = repairs + 1;
+  st.edges_added = added;
+  st.ms_repair = ms_since(t0);
+  if (stats != nullptr) *stats = st;
   return ok();
 }
 

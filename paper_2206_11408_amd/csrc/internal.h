@@ -107,6 +107,33 @@ hipError_t launch_gemm_nt(const float* A, int64_t rows, const float* B, int64_t 
 hipError_t launch_descend(const Tables& t, const float* Q, int64_t nq, int32_t* out, int32_t* calls,
                           hipStream_t s);
 
+// flat graph construction (graph.hip); the repair loop runs in api.hip
+hipError_t launch_drop_self(const int32_t* ids1, const float* d1, int64_t n, int k1, int k,
+                            int32_t* ids, float* dk, hipStream_t s);
+hipError_t launch_sym_keys_dst(int64_t n, int k, const int32_t* ids, const float* dk, uint32_t* keys,
+                               uint32_t* vals, hipStream_t s);
+hipError_t launch_sym_keys_src_d(int64_t n, int k, const int32_t* ids, const float* dk,
+                                 const uint32_t* perm, uint64_t* keys, hipStream_t s);
+hipError_t launch_sym_dedupe(int64_t n, int k, const int32_t* ids, const float* dk,
+                             const uint32_t* perm, uint32_t* flag, uint32_t* cnt, hipStream_t s);
+hipError_t launch_sym_fill(int64_t n, int k, const int32_t* ids, const float* dk, const uint32_t* perm,
+                           const uint32_t* flag, const uint32_t* pos, int32_t* nbr, float* nd,
+                           hipStream_t s);
+// hipCUB wrappers: tmp == nullptr queries tmp_bytes
+hipError_t radix_sort_u32(void* tmp, size_t& tmp_bytes, const uint32_t* kin, uint32_t* kout,
+                          const uint32_t* vin, uint32_t* vout, int64_t count, int end_bit, hipStream_t s);
+hipError_t radix_sort_u64(void* tmp, size_t& tmp_bytes, const uint64_t* kin, uint64_t* kout,
+                          const uint32_t* vin, uint32_t* vout, int64_t count, int end_bit, hipStream_t s);
+hipError_t exclusive_sum_u32(void* tmp, size_t& tmp_bytes, const uint32_t* in, uint32_t* out,
+                             int64_t count, hipStream_t s);
+hipError_t launch_prune(const float* data, int64_t n, int m, const uint32_t* indptr,
+                        const int32_t* nbr, const float* nd, int W, int32_t* out, hipStream_t s);
+hipError_t launch_degrees(const int32_t* G, int64_t n, int W, int32_t* deg, hipStream_t s);
+hipError_t launch_bfs_level(const int32_t* G, int W, const int32_t* frontier, int64_t fsize,
+                            uint32_t* reached, int32_t* next, uint32_t* next_count, hipStream_t s);
+hipError_t launch_nearest_free(const float* data, int64_t n, int m, int u, const uint32_t* reached,
+                               const int32_t* deg, int W, unsigned long long* best, hipStream_t s);
+
 // p[0..count) = value (a kernel, so that callers may capture it in a graph)
 hipError_t launch_fill_u32(void* p, uint32_t value, size_t count, hipStream_t s);
 

@@ -10,6 +10,7 @@ batch is checked by properties that hold at any size (returned distances are
 the exact squared distances of the returned ids, sorted by (d2, id); counter
 identities; recall against the exact kNN)."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -37,7 +38,9 @@ def c2_full():
     _say("c2 full: points")
     data, qs = make_points(spec)
     _say("c2 full: graph (exact 16-NN on the GPU, symmetrize, prune, repair)")
-    G, _, _ = build_graph(data, knn_k=spec.knn_k, max_degree=spec.max_degree, device="cuda")
+    t0 = time.time()
+    G, entry, gst = build_graph(data, knn_k=spec.knn_k, max_degree=spec.max_degree, device="cuda")
+    gst["seconds"] = time.time() - t0
     piv = pick_pivots(spec.n, 4096, spec.seed)
     d_data = torch.as_tensor(data, device="cuda")
     d_G = torch.as_tensor(G, device="cuda")
@@ -46,7 +49,8 @@ def c2_full():
     tab = api.finger_build_tables(d_data, d_G, rank=64, pivots=piv, seed=0)
     gt_ids, gt_d = api.finger_exact_knn(d_data, d_q, 10)
     sample = np.sort(np.random.default_rng(11).choice(spec.nq, N_SAMPLE, replace=False))
-    return dict(api=api, data=data, qs=qs, G=G, piv=piv, tab=tab, d_q=d_q, d_data=d_data,
+    return dict(api=api, data=data, qs=qs, G=G, entry=entry, gstats=gst, piv=piv, tab=tab, d_q=d_q,
+                d_data=d_data,
                 gt_ids=gt_ids.cpu().numpy(), gt_d=gt_d.cpu().numpy(), sample=sample)
 
 
@@ -120,3 +124,28 @@ def test_fullsize_finger_parity(c2_full):
     assert safe.mean() > 0.5
     assert same[safe].all()
     np.testing.assert_array_equal(ctr[s][safe][:, :6], oc[safe])
+
+
+def test_fullsize_graph_build_matches_the_workload_builder(c2_full):
+    """The library's on-device graph construction against the workload
+    builder (torch matmuls and a vectorised heuristic, a separate
+    implementation of the same recipe) on the 1M-point integer workload,
+    where every distance is exact: the graphs must be identical."""
+    import torch
+    api = c2_full["api"]
+    spec = SPECS["c2"]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    G, st = api.finger_build_graph(c2_full["d_data"], knn_k=spec.knn_k, max_degree=spec.max_degree,
+                                   entry=c2_full["entry"])
+    torch.cuda.synchronize()
+    secs = time.time() - t0
+    ref = c2_full["gstats"]
+    _say(f"graph build 1M x 128: library {secs:.2f} s ({st}); workload builder {ref['seconds']:.1f} s")
+    G = G.cpu().numpy()
+    same = (G == c2_full["G"]).all(1)
+    _say(f"identical rows: {same.mean():.6f}")
+    assert st["sym_degree_max"] == ref["sym_degree_max"]
+    assert st["components_before_repair"] == ref["components_before_repair"]
+    assert st["edges_added"] == ref["edges_added"]
+    np.testing.assert_array_equal(G, c2_full["G"])
