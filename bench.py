@@ -106,6 +106,12 @@ def main() -> int:
     ap.add_argument("--hierarchy", action="store_true",
                     help="also build HNSW-style upper layers (M = 16) and report both modes "
                          "started from the descent instead of the nearest pivot")
+    ap.add_argument("--mips", action="store_true",
+                    help="also report both modes under the inner-product metric (FINGER_IP) on the "
+                         "same points and graph, against inner-product ground truth")
+    ap.add_argument("--oracle-legs", type=int, default=0,
+                    help="time the float64 oracle on this many queries for the --mips and "
+                         "--hierarchy legs (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (the reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -149,10 +155,11 @@ def main() -> int:
     gt_ids = gt_ids.cpu().numpy()
     gt_d = gt_d.cpu().numpy()
 
-    def recall(ids, dist):
+    def recall(ids, dist, gt=None):
         # tie-aware: a returned id also counts if it sits at the 10th distance
-        kth = gt_d[:, 9:10]
-        hit = (ids[:, :10, None] == gt_ids[:, None, :10]).any(2) | ((dist[:, :10] <= kth) & (ids[:, :10] >= 0))
+        g_ids, g_d = gt if gt is not None else (gt_ids, gt_d)
+        kth = g_d[:, 9:10]
+        hit = (ids[:, :10, None] == g_ids[:, None, :10]).any(2) | ((dist[:, :10] <= kth) & (ids[:, :10] >= 0))
         return float(hit.mean())
 
     tables = {}
@@ -184,7 +191,7 @@ def main() -> int:
             p.kernel_events[1] = kev[1].cuda_event
         return api.finger_search(tab, d_q, p, out=out)
 
-    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT):
+    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT, gt=None):
         res = []
         for ef in EF_SWEEP:
             run(tab, mode, ef, prefetch=prefetch, entry=entry)
@@ -194,7 +201,7 @@ def main() -> int:
             ev[1].record()
             torch.cuda.synchronize()
             ms = ev[0].elapsed_time(ev[1])
-            rc = recall(ids.cpu().numpy(), dist.cpu().numpy())
+            rc = recall(ids.cpu().numpy(), dist.cpu().numpy(), gt)
             c = ctr.cpu().numpy()
             res.append(dict(ef=ef, recall=rc, ms=ms, qps=a.nq / ms * 1e3,
                             exact=float(c[:, 1].mean()), screened=float(c[:, 2].mean()),
@@ -208,7 +215,7 @@ def main() -> int:
         ok = [r for r in res if r["recall"] >= TARGET_RECALL]
         return res, (min(ok, key=lambda r: r["ef"]) if ok else max(res, key=lambda r: r["recall"]))
 
-    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0, entry=L.ENTRY_PIVOT):
+    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0, entry=L.ENTRY_PIVOT, gt=None):
         nq = a.nq
         out = (torch.empty((nq, 10), dtype=torch.int32, device=dev),
                torch.empty((nq, 10), dtype=torch.float32, device=dev),
@@ -254,7 +261,7 @@ def main() -> int:
         return dict(ef=ef, launch=geo, qps=nq * steps / total, ms_per_step=total / steps * 1e3,
                     gpu_ms_per_step=gpu_total / steps * 1e3,
                     kernel_ms=kavg, kernel_ms_min=float(np.min(kms)), alg_bytes=B,
-                    alg_gbs=B / (kavg * 1e-3) / 1e9, recall=recall(ids, dist),
+                    alg_gbs=B / (kavg * 1e-3) / 1e9, recall=recall(ids, dist, gt),
                     exact=float(ctr[:, 1].mean()), skipped=float(ctr[:, 3].mean()),
                     screened=float(ctr[:, 2].mean()))
 
@@ -303,6 +310,40 @@ def main() -> int:
                               speedup_vs_plain=round(tx["qps"] / tp["qps"], 4))
         log(f"finger {variant} timed: {tx}")
 
+    def oracle_qps(fn, count):
+        """The float64 oracle on `count` queries, one thread: queries/s."""
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            w0 = time.perf_counter()
+            fn(count)
+            return round(count / (time.perf_counter() - w0), 2)
+
+    mips = None
+    if a.mips:
+        from oracle.search import pivot_entries as o_piv, search_batch as o_search
+        tabI = api.finger_build_tables(d_data, d_G, rank=a.rank, metric=L.IP, pivots=piv, seed=0)
+        gi, gd = api.finger_exact_knn(d_data, d_q, 10, metric=L.IP)
+        gtI = (gi.cpu().numpy(), gd.cpu().numpy())
+        mips = {}
+        for nm, mode in (("plain", L.MODE_PLAIN), ("finger", L.MODE_FINGER)):
+            log(f"sweep {nm}, inner product")
+            sw, op = sweep(tabI, mode, gt=gtI)
+            th = timed(tabI, mode, op["ef"], a.steps, a.warmup, cb, fp8, gt=gtI)
+            log(f"{nm} timed, inner product: {th}")
+            mips[nm] = dict(ef=op["ef"], recall=round(th["recall"], 4), qps=round(th["qps"], 1),
+                            kernel_ms=round(th["kernel_ms"], 4), exact=round(th["exact"], 1),
+                            alg_gbs=round(th["alg_gbs"], 1), launch=th["launch"])
+        mips["speedup_vs_plain"] = round(mips["finger"]["qps"] / mips["plain"]["qps"], 4)
+        if a.oracle_legs:
+            from oracle.build import build as oracle_build
+            orc_t = oracle_build(data, G, a.rank, n_samples=100_000, seed=0)
+            qs_o = queries[:a.oracle_legs]
+            mips["oracle_qps_finger"] = oracle_qps(
+                lambda c: o_search(data, G, qs_o[:c], o_piv(qs_o[:c], data, piv, metric="ip"),
+                                   mips["finger"]["ef"], 10, mode="finger", tables=orc_t, metric="ip"),
+                a.oracle_legs)
+        tabI.close()
+
     hier = None
     if a.hierarchy:
         from workloads import build_hierarchy, draw_levels
@@ -331,6 +372,11 @@ def main() -> int:
                             kernel_ms=round(th["kernel_ms"], 4), exact=round(th["exact"], 1),
                             launch=th["launch"])
         hier["speedup_vs_plain"] = round(hier["finger"]["qps"] / hier["plain"]["qps"], 4)
+        if a.oracle_legs:
+            from oracle.search import hierarchy_entries
+            qs_o = queries[:a.oracle_legs]
+            hier["oracle_descent_qps"] = oracle_qps(
+                lambda c: hierarchy_entries(qs_o[:c], data, levels, upper), a.oracle_legs)
         hier["pivot_entries"] = dict(plain_exact=round(tp["exact"], 1), finger_exact=round(tf["exact"], 1))
 
     gated = None
@@ -444,10 +490,34 @@ def main() -> int:
         line["ablation"] = ablation_out
     if hier:
         line["descent_entries"] = hier
+    if mips:
+        line["inner_product"] = mips
+    if a.oracle_legs:
+        # graph construction at a size the float64 oracle finishes: the first
+        # 20,000 points, same recipe, GPU and oracle side by side
+        from oracle import graph as o_graph
+        sub = np.ascontiguousarray(data[:20_000])
+        e_sub = medoid(sub)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        api.finger_build_graph(torch.as_tensor(sub, device=dev), knn_k=spec.knn_k,
+                               max_degree=spec.max_degree, entry=e_sub)
+        torch.cuda.synchronize()
+        g_small = time.time() - t0
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.time()
+            o_graph.build(sub, spec.knn_k, spec.max_degree, e_sub)
+            o_small = time.time() - t0
+        gstats["n20000_gpu_s"] = round(g_small, 3)
+        gstats["n20000_oracle_s"] = round(o_small, 2)
     line["graph_build"] = {"seconds": round(graph_s, 3), "knn_ms": round(gstats["ms_knn"], 1),
                            "symmetrize_ms": round(gstats["ms_symmetrize"], 1),
                            "prune_ms": round(gstats["ms_prune"], 1), "repair_ms": round(gstats["ms_repair"], 1),
                            "knn_tflops": round(2.0 * a.n * a.n * spec.m / (gstats["ms_knn"] * 1e-3) / 1e12, 1)}
+    for key in ("n20000_gpu_s", "n20000_oracle_s"):
+        if key in gstats:
+            line["graph_build"][key] = gstats[key]
     print(json.dumps(line), flush=True)
     return 0
 
