@@ -328,16 +328,23 @@ typedef struct finger_graph_stats {
  *   out_graph [n][max_degree] int32 (device): rows of neighbour ids, -1
  *             padded; repair edges follow the row's own entries.
  *   stats     host, or NULL.
- * Synchronous; allocates its scratch (about 2nk * 40 bytes plus the exact
- * kNN's candidate lists) and frees it before returning.
+ * The kNN runs in query batches of at most 2^20 points.  Synchronous;
+ * allocates its scratch (about 2nk * 40 bytes plus one batch's kNN candidate
+ * lists) and frees it before returning.
  * Errors: EINVAL (NULL pointers, n < 2, m, knn_k outside 1..min(n - 1, 127),
  * max_degree outside 1..64, metric not L2/ANGULAR, entry out of range),
  * EOVERFLOW (2 n knn_k >= 2^31, or no reached node has a free slot for a
  * repair), ENOMEM, EDEVICE.
  */
+/* Progress report: called on the host after each finished step (phase
+ * "knn" per query batch with done/total queries, then "symmetrize", "prune"
+ * and "repair"); may be NULL. */
+typedef void (*finger_progress_fn)(const char* phase, int64_t done, int64_t total, void* user);
+
 FINGER_API int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k,
                                   int32_t max_degree, int32_t metric, int32_t entry,
                                   int32_t* out_graph, finger_graph_stats* stats /* host */,
+                                  finger_progress_fn progress, void* progress_user,
                                   void* stream);
 
 /* ------------------------------------------------------------ hierarchy */

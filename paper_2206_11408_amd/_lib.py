@@ -75,6 +75,9 @@ class TablesInfo(C.Structure):
     ]
 
 
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_char_p, C.c_int64, C.c_int64, C.c_void_p)
+
+
 class GraphStats(C.Structure):
     _fields_ = [
         ("sym_edges", C.c_int64), ("sym_degree_max", C.c_int32),
@@ -135,7 +138,8 @@ def load() -> C.CDLL:
     lib.finger_adam_step.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
                                      C.c_float, i32, vp]
     lib.finger_build_graph.restype = C.c_int
-    lib.finger_build_graph.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, P(GraphStats), vp]
+    lib.finger_build_graph.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, P(GraphStats),
+                                       PROGRESS_FN, vp, vp]
     lib.finger_hierarchy_attach.restype = C.c_int
     lib.finger_hierarchy_attach.argtypes = [vp, vp, vp, i64, i32]
     lib.finger_descend.restype = C.c_int

@@ -195,15 +195,17 @@ def finger_search(tables: Tables, queries: torch.Tensor, p: L.SearchParams | Non
 
 
 def finger_build_graph(data: torch.Tensor, knn_k: int = 16, max_degree: int = 32, entry: int = 0,
-                       metric: int = L.L2):
+                       metric: int = L.L2, progress=None):
     """The flat graph built on the GPU (finger_build_graph): returns
-    (graph int32 [n, max_degree] on the data's device, stats dict)."""
+    (graph int32 [n, max_degree] on the data's device, stats dict).
+    ``progress(phase, done, total)`` is called after each step."""
     data = _dev_f32(data)
     n, m = data.shape
     G = torch.empty((n, max_degree), dtype=torch.int32, device=data.device)
     st = L.GraphStats()
+    cb = L.PROGRESS_FN(lambda ph, d, t, _u: progress(ph.decode(), d, t)) if progress else L.PROGRESS_FN()
     L.check(L.load().finger_build_graph(data.data_ptr(), n, m, knn_k, max_degree, metric, entry,
-                                        G.data_ptr(), C.byref(st), _stream()))
+                                        G.data_ptr(), C.byref(st), cb, None, _stream()))
     return G, {name: getattr(st, name) for name, _ in L.GraphStats._fields_}
 
 

@@ -629,7 +629,7 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
 
 int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, int32_t max_degree,
                        int32_t metric, int32_t entry, int32_t* out_graph, finger_graph_stats* stats,
-                       void* stream) {
+                       finger_progress_fn progress, void* progress_user, void* stream) {
   using namespace finger;
   if (data == nullptr || out_graph == nullptr) return fail(FINGER_EINVAL, "NULL data or out_graph");
   if (n < 2) return fail(FINGER_EINVAL, "n = %lld < 2", (long long)n);
@@ -666,18 +666,23 @@ int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, i
     HIPCHK(launch_normalize_rows(data, n, m, normed.p, s));
     X = normed.p;
   }
+  const int64_t batch = std::min<int64_t>(n, int64_t(1) << 20);
   DevBuf<char> kws;
   DevBuf<int32_t> ids1, ids;
   DevBuf<float> d1, dk;
-  alloc(kws, exact_knn_ws_bytes(n, m, n, k1), "kNN workspace");
-  alloc(ids1, (size_t)n * k1 * 4, "kNN ids");
-  alloc(d1, (size_t)n * k1 * 4, "kNN distances");
+  alloc(kws, exact_knn_ws_bytes(n, m, batch, k1), "kNN workspace");
+  alloc(ids1, (size_t)batch * k1 * 4, "kNN ids");
+  alloc(d1, (size_t)batch * k1 * 4, "kNN distances");
   alloc(ids, (size_t)nk * 4, "kNN lists");
   alloc(dk, (size_t)nk * 4, "kNN list distances");
   if (rc != FINGER_OK) return rc;
-  HIPCHK(launch_exact_knn(X, n, m, X, n, k1, FINGER_L2, ids1.p, d1.p, kws.p, s));
-  HIPCHK(launch_drop_self(ids1.p, d1.p, n, k1, k, ids.p, dk.p, s));
-  HIPCHK(hipStreamSynchronize(s));
+  for (int64_t b0 = 0; b0 < n; b0 += batch) {
+    const int64_t nb = std::min(batch, n - b0);
+    HIPCHK(launch_exact_knn(X, n, m, X + b0 * m, nb, k1, FINGER_L2, ids1.p, d1.p, kws.p, s));
+    HIPCHK(launch_drop_self(ids1.p, d1.p, nb, k1, k, ids.p + b0 * k, dk.p + b0 * k, b0, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (progress) progress("knn", b0 + nb, n, progress_user);
+  }
   st.ms_knn = ms_since(t0);
   kws.reset();
   ids1.reset();
@@ -741,12 +746,14 @@ int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, i
   HIPCHK(launch_sym_fill(n, k, ids.p, dk.p, va.p, ka.p, kb.p, nbr.p, nd.p, s));
   HIPCHK(hipStreamSynchronize(s));
   st.ms_symmetrize = ms_since(t0);
+  if (progress) progress("symmetrize", total, total, progress_user);
 
   // 3. neighbour-selection heuristic on long rows
   t0 = now();
   HIPCHK(launch_prune(X, n, m, indptr.p, nbr.p, nd.p, W, out_graph, s));
   HIPCHK(hipStreamSynchronize(s));
   st.ms_prune = ms_since(t0);
+  if (progress) progress("prune", n, n, progress_user);
 
   // 4. reachability repair from the entry (host loop; each step depends on the last)
   t0 = now();
@@ -837,6 +844,7 @@ int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, i
   st.components_before_repair = repairs + 1;
   st.edges_added = added;
   st.ms_repair = ms_since(t0);
+  if (progress) progress("repair", repairs, repairs, progress_user);
   if (stats != nullptr) *stats = st;
   return ok();
 }

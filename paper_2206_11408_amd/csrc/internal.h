@@ -109,7 +109,7 @@ hipError_t launch_descend(const Tables& t, const float* Q, int64_t nq, int32_t* 
 
 // flat graph construction (graph.hip); the repair loop runs in api.hip
 hipError_t launch_drop_self(const int32_t* ids1, const float* d1, int64_t n, int k1, int k,
-                            int32_t* ids, float* dk, hipStream_t s);
+                            int32_t* ids, float* dk, int64_t first, hipStream_t s);
 hipError_t launch_sym_keys_dst(int64_t n, int k, const int32_t* ids, const float* dk, uint32_t* keys,
                                uint32_t* vals, hipStream_t s);
 hipError_t launch_sym_keys_src_d(int64_t n, int k, const int32_t* ids, const float* dk,

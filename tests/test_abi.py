@@ -167,13 +167,14 @@ def test_null_handle_search_calls():
     assert lib.finger_tables_info_get(None, C.byref(info)) == L.FINGER_EINVAL
     assert lib.finger_hierarchy_attach(None, 1 << 20, 1 << 20, 4, 16) == L.FINGER_EINVAL
     assert lib.finger_descend(None, 1 << 20, 4, 1 << 20, None, None) == L.FINGER_EINVAL
-    assert lib.finger_build_graph(None, 100, 32, 16, 32, 0, 0, 1 << 20, None, None) == L.FINGER_EINVAL
+    assert lib.finger_build_graph(None, 100, 32, 16, 32, 0, 0, 1 << 20, None, L.PROGRESS_FN(), None,
+                                  None) == L.FINGER_EINVAL
     # argument checks run before any device work
     for bad in [dict(n=1), dict(m=30), dict(k=0), dict(k=100), dict(W=65), dict(metric=2),
                 dict(entry=100), dict(n=1 << 27, k=16)]:
         a = dict(n=100, m=32, k=16, W=32, metric=0, entry=0) | bad
         st = lib.finger_build_graph(1 << 20, a["n"], a["m"], a["k"], a["W"], a["metric"], a["entry"],
-                                    1 << 20, None, None)
+                                    1 << 20, None, L.PROGRESS_FN(), None, None)
         assert st in (L.FINGER_EINVAL, L.FINGER_EOVERFLOW), bad
     lib.finger_free_tables(None)  # no-op
 
