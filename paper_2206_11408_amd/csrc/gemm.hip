@@ -3,7 +3,9 @@
 //     once per query) plus, with pivots, the scores |x|^2 - 2 q.x that pick
 //     each query's start point;
 //   * the node table P c of every node;
-//   * brute-force kNN (the recall ground truth of Section 1).
+//   * brute-force kNN (the recall ground truth of Section 1, and the graph
+//     build's self-join): candidate scores in split bf16 precision, then an
+//     exact float32 re-rank.
 // All are C[i][j] = sum_k A[i][k] B[j][k] with A, B row-major and k
 // contiguous.  One 256-thread block computes a 64 x 64 tile; each wave owns
 // a 32 x 32 quarter as 2 x 2 blocks of v_mfma_f32_16x16x4f32.  K advances
@@ -427,6 +429,85 @@ namespace {
 
 constexpr int kKnnSlack = 32;
 
+// Candidate scores for the kNN on the bf16 matrix cores, in split precision:
+// each float x is staged as hi = bf16(x) and lo = bf16(x - hi), and
+// A.B ~ hi.hi' + hi.lo' + lo.hi' (the dropped lo.lo' term is below 2^-16 of
+// |x||y|), accumulated in float32 by v_mfma_f32_16x16x32_bf16.  The scores
+// only choose the k + 32 candidates that k_knn_final re-ranks by exact
+// float32 differences.  LDS: hi/lo tiles of A and B, 64 rows x 32 k, rows
+// padded to 40 elements (80 bytes) so a lane's 16-byte fragment read stays
+// aligned.
+constexpr int kX3Row = 40;
+constexpr int kX3Tile = BM * kX3Row;                      // elements per hi or lo tile
+constexpr int kX3Bytes = 4 * kX3Tile * 2;                 // Ahi, Alo, Bhi, Blo
+static_assert(kX3Bytes >= BM * 65 * 4, "the score tile reuses the staging area");
+
+__device__ __forceinline__ void stage_x3(const float* __restrict__ A, int64_t rows,
+                                         const float* __restrict__ B, int64_t cols, int K,
+                                         int64_t r0, int64_t c0, int k0, __bf16* S) {
+  const int t = threadIdx.x;
+  __bf16* Ahi = S;
+  __bf16* Alo = S + kX3Tile;
+  __bf16* Bhi = S + 2 * kX3Tile;
+  __bf16* Blo = S + 3 * kX3Tile;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int row = (t >> 3) + 32 * h;
+    const int kc = (t & 7) * 4;
+    float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+    const int kk = k0 + kc;
+    if (kk < K) {
+      if (r0 + row < rows) va = *reinterpret_cast<const float4*>(A + (r0 + row) * (int64_t)K + kk);
+      if (c0 + row < cols) vb = *reinterpret_cast<const float4*>(B + (c0 + row) * (int64_t)K + kk);
+    }
+    const float xa[4] = {va.x, va.y, va.z, va.w};
+    const float xb[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const __bf16 ha = (__bf16)xa[e], hb = (__bf16)xb[e];
+      Ahi[row * kX3Row + kc + e] = ha;
+      Alo[row * kX3Row + kc + e] = (__bf16)(xa[e] - (float)ha);
+      Bhi[row * kX3Row + kc + e] = hb;
+      Blo[row * kX3Row + kc + e] = (__bf16)(xb[e] - (float)hb);
+    }
+  }
+}
+
+// acc[bi][bj] covers rows wr + 16 bi + 4 (l/16) + v, cols wc + 16 bj + l%16
+// (the same layout as tile_mma)
+__device__ __forceinline__ void tile_mma_x3(const float* __restrict__ A, int64_t rows,
+                                            const float* __restrict__ B, int64_t cols, int K,
+                                            int64_t r0, int64_t c0, __bf16* S, f4v acc[2][2]) {
+  const int w = threadIdx.x / 64, l = threadIdx.x & 63;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int fo = (l & 15) * kX3Row + 8 * (l >> 4);   // this lane's fragment in a 16-row block
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    stage_x3(A, rows, B, cols, K, r0, c0, k0, S);
+    __syncthreads();
+    b8v ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ah[i] = *reinterpret_cast<const b8v*>(S + (wr + 16 * i) * kX3Row + fo);
+      al[i] = *reinterpret_cast<const b8v*>(S + kX3Tile + (wr + 16 * i) * kX3Row + fo);
+      bh[i] = *reinterpret_cast<const b8v*>(S + 2 * kX3Tile + (wc + 16 * i) * kX3Row + fo);
+      bl[i] = *reinterpret_cast<const b8v*>(S + 3 * kX3Tile + (wc + 16 * i) * kX3Row + fo);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+  }
+}
+
 // Each block: 64 queries x a contiguous range of data columns.  The running
 // best KK (approximate d2, id) per query live in LDS as sorted lists.
 __global__ void __launch_bounds__(256) k_knn_tiles(const float* Q, int64_t nq, const float* X,
@@ -434,9 +515,8 @@ __global__ void __launch_bounds__(256) k_knn_tiles(const float* Q, int64_t nq, c
                                                    const float* xn, int KK, int64_t chunk,
                                                    uint64_t* out, int nchunks, int ip) {
   extern __shared__ __align__(16) char smem[];
-  float* As = reinterpret_cast<float*>(smem);
-  float* Bs = As + BM * LDT;
-  uint64_t* lists = reinterpret_cast<uint64_t*>(smem + 2 * BM * LDT * sizeof(float));
+  __bf16* S = reinterpret_cast<__bf16*>(smem);
+  uint64_t* lists = reinterpret_cast<uint64_t*>(smem + kX3Bytes);
   const int64_t r0 = (int64_t)blockIdx.y * BM;
   const int64_t cbeg = (int64_t)blockIdx.x * chunk;
   const int64_t cend = min(n, cbeg + chunk);
@@ -448,9 +528,9 @@ __global__ void __launch_bounds__(256) k_knn_tiles(const float* Q, int64_t nq, c
   for (int i = threadIdx.x; i < BM; i += blockDim.x) cnts[i] = 0;
   for (int64_t c0 = cbeg; c0 < cend; c0 += BN) {
     f4v acc[2][2];
-    tile_mma(Q, nq, X, cend, K, r0, c0, As, Bs, acc);
+    tile_mma_x3(Q, nq, X, cend, K, r0, c0, S, acc);
     __syncthreads();
-    float* Ct = As;  // 64 x 65 tile of approximate d2
+    float* Ct = reinterpret_cast<float*>(smem);  // 64 x 65 tile of approximate d2
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -629,7 +709,7 @@ hipError_t launch_exact_knn(const float* data, int64_t n, int m, const float* Q,
   if (e != hipSuccess) return e;
   const int64_t ntile = (n + BN - 1) / BN;
   const int64_t chunk = (ntile + nch - 1) / nch * BN;
-  const int lds = 2 * BM * LDT * (int)sizeof(float) + BM * KK * 8 + BM * 4 + 4 * 64 * 8;
+  const int lds = kX3Bytes + BM * KK * 8 + BM * 4 + 4 * 64 * 8;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_knn_tiles),
                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
