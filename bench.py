@@ -386,7 +386,7 @@ def main() -> int:
         _, tr_q = make_points(tr_spec)   # same mixture; rows after the first nq are new draws
         t0 = time.time()
         info = gate_mod.fit_gate(tabF, torch.as_tensor(tr_q[a.nq:], device=dev), ef=op_f["ef"],
-                                 hidden=64, epochs=2, batch=4096, lr=2e-3, capacity=1 << 24,
+                                 hidden=64, epochs=2, batch=4096, lr=2e-3, capacity=20_000_000,
                                  log=log)
         torch.cuda.synchronize()
         log(f"gate trained in {time.time() - t0:.1f}s on {info['rows']} rows "

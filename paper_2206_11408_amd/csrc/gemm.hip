@@ -1,4 +1,4 @@
-// Dense contractions of the path on the fp32 matrix cores (MFMA):
+// Dense contractions of the path on the matrix cores (MFMA):
 //   * query preparation: Pq = P q for a batch (Supplementary G computes Pq
 //     once per query) plus, with pivots, the scores |x|^2 - 2 q.x that pick
 //     each query's start point;
@@ -8,8 +8,10 @@
 //     exact float32 re-rank.
 // All are C[i][j] = sum_k A[i][k] B[j][k] with A, B row-major and k
 // contiguous.  One 256-thread block computes a 64 x 64 tile; each wave owns
-// a 32 x 32 quarter as 2 x 2 blocks of v_mfma_f32_16x16x4f32.  K advances
-// in slabs of 32 staged through LDS.
+// a 32 x 32 quarter as 2 x 2 blocks of 16 x 16 MFMA tiles (fp32
+// v_mfma_f32_16x16x4f32 for Pq and P c; the pivot scores and the kNN
+// candidate scores use the bf16 instructions described with them).  K
+// advances in slabs of 32 staged through LDS.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
