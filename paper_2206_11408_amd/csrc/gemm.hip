@@ -439,6 +439,7 @@ constexpr int kKnnSlack = 32;
 // float32 differences.  LDS: hi/lo tiles of A and B, 64 rows x 32 k, rows
 // padded to 40 elements (80 bytes) so a lane's 16-byte fragment read stays
 // aligned.
+typedef __bf16 b4v __attribute__((ext_vector_type(4)));
 constexpr int kX3Row = 40;
 constexpr int kX3Tile = BM * kX3Row;                      // elements per hi or lo tile
 constexpr int kX3Bytes = 4 * kX3Tile * 2;                 // Ahi, Alo, Bhi, Blo
@@ -464,14 +465,20 @@ __device__ __forceinline__ void stage_x3(const float* __restrict__ A, int64_t ro
     }
     const float xa[4] = {va.x, va.y, va.z, va.w};
     const float xb[4] = {vb.x, vb.y, vb.z, vb.w};
+    b4v ha, la, hb, lb;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const __bf16 ha = (__bf16)xa[e], hb = (__bf16)xb[e];
-      Ahi[row * kX3Row + kc + e] = ha;
-      Alo[row * kX3Row + kc + e] = (__bf16)(xa[e] - (float)ha);
-      Bhi[row * kX3Row + kc + e] = hb;
-      Blo[row * kX3Row + kc + e] = (__bf16)(xb[e] - (float)hb);
+      ha[e] = (__bf16)xa[e];
+      la[e] = (__bf16)(xa[e] - (float)ha[e]);
+      hb[e] = (__bf16)xb[e];
+      lb[e] = (__bf16)(xb[e] - (float)hb[e]);
     }
+    // four elements = one 8-byte LDS write per tile (row * 80 + kc * 2 is
+    // 8-byte aligned)
+    *reinterpret_cast<b4v*>(Ahi + row * kX3Row + kc) = ha;
+    *reinterpret_cast<b4v*>(Alo + row * kX3Row + kc) = la;
+    *reinterpret_cast<b4v*>(Bhi + row * kX3Row + kc) = hb;
+    *reinterpret_cast<b4v*>(Blo + row * kX3Row + kc) = lb;
   }
 }
 
@@ -548,16 +555,29 @@ __global__ void __launch_bounds__(256) k_knn_tiles(const float* Q, int64_t nq, c
           Ct[rr * 65 + cl] = d;
         }
     __syncthreads();
-    for (int rr = w; rr < BM; rr += 4) {
-      uint64_t* L = lists + rr * KK;
+    // this wave's 16 rows: read every row's score and current worst key
+    // first, so the LDS reads are in flight together (most rows admit
+    // nothing once their lists are full)
+    float dr[BM / 4];
+    uint64_t wr_[BM / 4];
+#pragma unroll
+    for (int s4 = 0; s4 < BM / 4; ++s4) {
+      const int rr = w + 4 * s4;
+      dr[s4] = Ct[rr * 65 + l];
       const int cnt = cnts[rr];
-      const uint64_t worst = cnt < KK ? ~0ull : L[KK - 1];
-      const float d = Ct[rr * 65 + l];
+      wr_[s4] = cnt < KK ? ~0ull : lists[rr * KK + KK - 1];
+    }
+#pragma unroll 1
+    for (int s4 = 0; s4 < BM / 4; ++s4) {
+      const int rr = w + 4 * s4;
+      uint64_t* L = lists + rr * KK;
+      const float d = dr[s4];
       const uint64_t key = (d < __int_as_float(0x7f800000)) ? make_key(d, (int)(c0 + l)) : ~0ull;
-      const bool in = key < worst;
+      const bool in = key < wr_[s4];
       const uint64_t bm = ballot(in);
       const int na = popc64(bm);
       if (na == 0) continue;
+      const int cnt = cnts[rr];
       const uint64_t v = bitonic_sort<64>(in ? key : ~0ull);
       nk[l] = v;
       wave_lds_sync();
