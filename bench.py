@@ -112,6 +112,9 @@ def main() -> int:
     ap.add_argument("--oracle-legs", type=int, default=0,
                     help="time the float64 oracle on this many queries for the --mips and "
                          "--hierarchy legs (0 = skip)")
+    ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=False,
+                    help="time the step as a replay of a captured HIP graph (kernel times "
+                         "still come from the eager launches)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (the reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -255,10 +258,41 @@ def main() -> int:
         total = time.perf_counter() - t0
         gpu_total = ev[0].elapsed_time(ev[1]) * 1e-3
         kms = [e0.elapsed_time(e1) for e0, e1 in pairs]
+        graph_step = None
+        if a.graph:
+            # the same step captured once in a HIP graph and replayed: query
+            # preparation and search without per-launch host gaps
+            pg = api.search_params(mode=mode, k=10, ef=ef, entry=entry,
+                                   code_prefetch=geo.get("code_prefetch", prefetch),
+                                   waves_per_cu=geo.get("waves_per_cu", 0),
+                                   persistent=geo.get("persistent", 0),
+                                   visited_capacity=geo.get("visited_capacity", 0))
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                api.finger_search(tab, d_q, pg, out=out)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            cg = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(cg):
+                api.finger_search(tab, d_q, pg, out=out)
+            for _ in range(warmup):
+                cg.replay()
+            torch.cuda.synchronize()
+            g0 = time.perf_counter()
+            for _ in range(steps):
+                cg.replay()
+            torch.cuda.synchronize()
+            graph_step = (time.perf_counter() - g0) / steps
+            del cg
         ids, dist, ctr = (x.cpu().numpy() for x in out)
         B = algorithmic_bytes(ctr, spec.m, spec.max_degree, a.rank if mode else 0, code_bytes, 10, fp8)
         kavg = float(np.mean(kms))
+        if graph_step is not None:
+            log(f"  graph replay: {graph_step * 1e3:.4f} ms per step (eager {total / steps * 1e3:.4f})")
+            total = graph_step * steps
         return dict(ef=ef, launch=geo, qps=nq * steps / total, ms_per_step=total / steps * 1e3,
+                    graph=graph_step is not None,
                     gpu_ms_per_step=gpu_total / steps * 1e3,
                     kernel_ms=kavg, kernel_ms_min=float(np.min(kms)), alg_bytes=B,
                     alg_gbs=B / (kavg * 1e-3) / 1e9, recall=recall(ids, dist, gt),

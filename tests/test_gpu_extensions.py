@@ -316,3 +316,41 @@ def test_angular_metric_normalizes_both_sides(api):
     from oracle.knn import brute_force_knn
     bi, bd = brute_force_knn(nd, nq, 10)
     assert (gi.cpu().numpy() == bi).all(1).mean() >= 0.99
+
+
+def test_search_replays_from_a_captured_graph():
+    """finger_search enqueues kernels only (its scratch is cleared by fill
+    kernels), so a caller may capture it in a HIP graph: every replay, with
+    eager work and synchronizations between replays, equals the eager call."""
+    import torch
+    from paper_2206_11408_amd import api
+    torch.cuda.init()
+    data, qs, G, _, piv = helpers.c2_small()
+    tab = api.finger_build_tables(torch.as_tensor(data, device="cuda"), torch.as_tensor(G, device="cuda"),
+                                  rank=32, pivots=piv, seed=0)
+    d_q = torch.as_tensor(qs, device="cuda")
+    for mode, persistent in ((0, 0), (1, 1), (1, 0)):
+        p = api.search_params(mode=mode, k=10, ef=48, entry=-1, persistent=persistent)
+        eager = [x.clone() for x in api.finger_search(tab, d_q, p)]
+        out = tuple(torch.empty_like(x) for x in eager)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            api.finger_search(tab, d_q, p, out=out)      # warm-up on a side stream
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            api.finger_search(tab, d_q, p, out=out)
+        for rep in range(4):
+            for x in out:
+                x.fill_(-7)
+            g.replay()
+            torch.cuda.synchronize()
+            for a, b in zip(out, eager):
+                assert torch.equal(a, b), (mode, persistent, rep)
+            # eager work between replays, on the same tables and workspace
+            api.finger_search(tab, d_q[: 17 * (rep + 1)], mode=mode, k=10, ef=32, entry=-1)
+            torch.cuda.synchronize()
+        _say(f"graph replay mode={mode} persistent={persistent}: 4 replays identical to the eager call")
+    tab.close()
