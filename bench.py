@@ -106,6 +106,9 @@ def main() -> int:
     ap.add_argument("--hierarchy", action="store_true",
                     help="also build HNSW-style upper layers (M = 16) and report both modes "
                          "started from the descent instead of the nearest pivot")
+    ap.add_argument("--spectrum", action=argparse.BooleanOptionalAction, default=True,
+                    help="also report plain and FINGER (r = 64 and r = 16) on the same recipe with a "
+                         "decaying noise spectrum calibrated to the paper's SIFT rank")
     ap.add_argument("--mips", action="store_true",
                     help="also report both modes under the inner-product metric (FINGER_IP) on the "
                          "same points and graph, against inner-product ground truth")
@@ -143,6 +146,7 @@ def main() -> int:
     log(f"points n={a.n} m={spec.m} nq={a.nq} in {time.time() - t0:.1f}s")
     d_data = torch.as_tensor(data, device=dev)
     d_q = torch.as_tensor(queries, device=dev)
+    d_q_main = d_q
     t0 = time.time()
     d_G, gstats = api.finger_build_graph(d_data, knn_k=spec.knn_k, max_degree=spec.max_degree,
                                          entry=medoid(data))
@@ -187,20 +191,20 @@ def main() -> int:
 
     launch = {}   # (mode, code) -> tuned launch settings
 
-    def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0, entry=L.ENTRY_PIVOT):
+    def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0, entry=L.ENTRY_PIVOT, queries=None):
         p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, code_prefetch=prefetch)
         if time_kernel:
             p.kernel_events[0] = kev[0].cuda_event
             p.kernel_events[1] = kev[1].cuda_event
-        return api.finger_search(tab, d_q, p, out=out)
+        return api.finger_search(tab, d_q if queries is None else queries, p, out=out)
 
-    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT, gt=None):
+    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT, gt=None, queries=None):
         res = []
         for ef in EF_SWEEP:
-            run(tab, mode, ef, prefetch=prefetch, entry=entry)
+            run(tab, mode, ef, prefetch=prefetch, entry=entry, queries=queries)
             torch.cuda.synchronize()
             ev[0].record()
-            ids, dist, ctr = run(tab, mode, ef, prefetch=prefetch, entry=entry)
+            ids, dist, ctr = run(tab, mode, ef, prefetch=prefetch, entry=entry, queries=queries)
             ev[1].record()
             torch.cuda.synchronize()
             ms = ev[0].elapsed_time(ev[1])
@@ -218,8 +222,10 @@ def main() -> int:
         ok = [r for r in res if r["recall"] >= TARGET_RECALL]
         return res, (min(ok, key=lambda r: r["ef"]) if ok else max(res, key=lambda r: r["recall"]))
 
-    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0, entry=L.ENTRY_PIVOT, gt=None):
+    def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0, entry=L.ENTRY_PIVOT, gt=None,
+              queries=None, rank=None):
         nq = a.nq
+        d_q = d_q_main if queries is None else queries
         out = (torch.empty((nq, 10), dtype=torch.int32, device=dev),
                torch.empty((nq, 10), dtype=torch.float32, device=dev),
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
@@ -286,7 +292,8 @@ def main() -> int:
             graph_step = (time.perf_counter() - g0) / steps
             del cg
         ids, dist, ctr = (x.cpu().numpy() for x in out)
-        B = algorithmic_bytes(ctr, spec.m, spec.max_degree, a.rank if mode else 0, code_bytes, 10, fp8)
+        B = algorithmic_bytes(ctr, spec.m, spec.max_degree, (a.rank if rank is None else rank) if mode else 0,
+                              code_bytes, 10, fp8)
         kavg = float(np.mean(kms))
         if graph_step is not None:
             log(f"  graph replay: {graph_step * 1e3:.4f} ms per step (eager {total / steps * 1e3:.4f})")
@@ -377,6 +384,47 @@ def main() -> int:
                                    mips["finger"]["ef"], 10, mode="finger", tables=orc_t, metric="ip"),
                 a.oracle_legs)
         tabI.close()
+
+    sift = None
+    if a.spectrum:
+        # the same recipe with a decaying noise spectrum (the rank rule settles
+        # on r = 16 there, as the paper reports for SIFT-1M-128): plain,
+        # FINGER at the configured rank and FINGER at the rule's rank
+        spec2 = SPECS["c2s"].scaled(n=a.n, n_centers=a.clusters, nq=a.nq)
+        data2, q2 = make_points(spec2)
+        dd2 = torch.as_tensor(data2, device=dev)
+        dq2 = torch.as_tensor(q2, device=dev)
+        t0 = time.time()
+        dG2, gst2 = api.finger_build_graph(dd2, knn_k=spec2.knn_k, max_degree=spec2.max_degree,
+                                           entry=medoid(data2))
+        torch.cuda.synchronize()
+        log(f"c2s graph in {time.time() - t0:.1f}s: {gst2}")
+        piv2 = pick_pivots(a.n, a.pivots, spec2.seed)
+        gi2, gd2 = api.finger_exact_knn(dd2, dq2, 10)
+        gt2 = (gi2.cpu().numpy(), gd2.cpu().numpy())
+        t64 = api.finger_build_tables(dd2, dG2, rank=a.rank, pivots=piv2, seed=0)
+        t16 = api.finger_build_tables(dd2, dG2, rank=16, pivots=piv2, seed=0)
+        sift = {"workload": (f"c2s: n={a.n} m=128 int 0-255, {a.clusters}-cluster mixture with noise "
+                             f"spectrum i^-{spec2.decay}, 16-NN sym pruned deg 32, {a.pivots} pivots, "
+                             f"nq={a.nq}, K=10"),
+                "corr_xy_r16": round(t16.info()["corr_xy"], 4),
+                "corr_xy_r64": round(t64.info()["corr_xy"], 4)}
+        for nm, tab, mode, r in (("plain", t64, L.MODE_PLAIN, 0), ("finger_r64", t64, L.MODE_FINGER, a.rank),
+                                 ("finger_r16", t16, L.MODE_FINGER, 16)):
+            log(f"sweep {nm} (c2s)")
+            sw, op = sweep(tab, mode, gt=gt2, queries=dq2)
+            th = timed(tab, mode, op["ef"], a.steps, a.warmup, 4, False, gt=gt2, queries=dq2, rank=r)
+            log(f"{nm} timed (c2s): {th}")
+            sift[nm] = dict(ef=op["ef"], recall=round(th["recall"], 4), qps=round(th["qps"], 1),
+                            kernel_ms=round(th["kernel_ms"], 4), exact=round(th["exact"], 1),
+                            screened=round(th["screened"], 1), skipped=round(th["skipped"], 1),
+                            alg_gbs=round(th["alg_gbs"], 1),
+                            hbm_frac=round(th["alg_gbs"] / PEAK_HBM_GBS, 4), launch=th["launch"])
+        sift["speedup_r64_vs_plain"] = round(sift["finger_r64"]["qps"] / sift["plain"]["qps"], 4)
+        sift["speedup_r16_vs_plain"] = round(sift["finger_r16"]["qps"] / sift["plain"]["qps"], 4)
+        t64.close()
+        t16.close()
+        del dd2, dq2, dG2
 
     hier = None
     if a.hierarchy:
@@ -526,6 +574,8 @@ def main() -> int:
         line["descent_entries"] = hier
     if mips:
         line["inner_product"] = mips
+    if sift:
+        line["sift_like_spectrum"] = sift
     if a.oracle_legs:
         # graph construction at a size the float64 oracle finishes: the first
         # 20,000 points, same recipe, GPU and oracle side by side

@@ -22,6 +22,11 @@ class WorkloadSpec:
       "int"     centres ~ U[0, 128)^m, x = clip(rint(centre + sigma*N), 0, 255)
       "uniform" centres ~ U[0, 1)^m,   x = centre + sigma * N(0, I)
       "heavy"   centres ~ N(0, I), x = centre + sigma * Student-t(3), unit-normalised
+
+    decay > 0 replaces the isotropic noise z by z A, A = Q diag(s) Q^T with a
+    seeded random rotation Q and s_i proportional to i^-decay, scaled so that
+    the mean of s_i^2 is 1 (the same total noise variance): a decaying
+    principal-component spectrum, as real descriptors have.
     """
 
     name: str
@@ -32,6 +37,7 @@ class WorkloadSpec:
     sigma: float
     nq: int
     seed: int = 0
+    decay: float = 0.0       # noise spectrum exponent (0 = isotropic)
     knn_k: int = 16          # exact kNN size before symmetrization
     max_degree: int = 32     # graph row width after pruning
     extra: dict = field(default_factory=dict)
@@ -50,6 +56,10 @@ SPECS = {
     "c1": WorkloadSpec("c1", "gauss", 10_000, 32, 100, 0.3, 1_000, seed=0),
     # bandwidth workload: integer-valued 128-d, 1000 clusters
     "c2": WorkloadSpec("c2", "int", 1_000_000, 128, 1_000, 24.0, 10_000, seed=0),
+    # the same with a decaying noise spectrum, calibrated so that the rank
+    # rule of Supplementary E (correlation of X and Y >= 0.7) settles on
+    # r = 16, the rank the paper reports for SIFT-1M-128
+    "c2s": WorkloadSpec("c2s", "int", 1_000_000, 128, 1_000, 24.0, 10_000, seed=0, decay=0.3),
     # precision workloads
     "c3a": WorkloadSpec("c3a", "uniform", 1_000_000, 960, 1_000, 0.1, 10_000, seed=0),
     "c3b": WorkloadSpec("c3b", "heavy", 1_200_000, 100, 1_000, 1.0, 10_000, seed=0),
@@ -59,7 +69,7 @@ SPECS = {
 
 
 def _draw(rng: np.random.Generator, spec: WorkloadSpec, centers: np.ndarray,
-          count: int) -> np.ndarray:
+          count: int, mix: np.ndarray | None = None) -> np.ndarray:
     labels = rng.integers(0, spec.n_centers, size=count)
     m = spec.m
     out = np.empty((count, m), dtype=np.float32)
@@ -71,6 +81,8 @@ def _draw(rng: np.random.Generator, spec: WorkloadSpec, centers: np.ndarray,
             noise = rng.standard_t(3.0, size=(e - s, m))
         else:
             noise = rng.standard_normal(size=(e - s, m))
+        if mix is not None:
+            noise = noise @ mix
         x = c + spec.sigma * noise
         if spec.kind == "int":
             x = np.clip(np.rint(x), 0, 255)
@@ -102,6 +114,15 @@ def gaussian_projection(rank: int, m: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((rank, m))
 
 
+def noise_mix(spec: WorkloadSpec, rng: np.random.Generator) -> np.ndarray:
+    """A = Q diag(s) Q^T for spec.decay > 0 (see WorkloadSpec)."""
+    m = spec.m
+    Q, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    s = np.arange(1, m + 1, dtype=np.float64) ** (-spec.decay)
+    s /= np.sqrt((s * s).mean())
+    return (Q * s) @ Q.T
+
+
 def make_points(spec: WorkloadSpec) -> tuple[np.ndarray, np.ndarray]:
     """Return (data [n, m], queries [nq, m]) as C-contiguous float32."""
     rng = np.random.default_rng(spec.seed)
@@ -113,6 +134,7 @@ def make_points(spec: WorkloadSpec) -> tuple[np.ndarray, np.ndarray]:
         centers = rng.uniform(0.0, 1.0, size=(spec.n_centers, spec.m))
     else:
         raise ValueError(f"unknown kind {spec.kind}")
-    data = _draw(rng, spec, centers, spec.n)
-    queries = _draw(rng, spec, centers, spec.nq)
+    mix = noise_mix(spec, rng) if spec.decay > 0 else None
+    data = _draw(rng, spec, centers, spec.n, mix)
+    queries = _draw(rng, spec, centers, spec.nq, mix)
     return np.ascontiguousarray(data), np.ascontiguousarray(queries)
