@@ -109,6 +109,8 @@ def main() -> int:
     ap.add_argument("--spectrum", action=argparse.BooleanOptionalAction, default=True,
                     help="also report plain and FINGER (r = 64 and r = 16) on the same recipe with a "
                          "decaying noise spectrum calibrated to the paper's SIFT rank")
+    ap.add_argument("--spectrum-codes", default="",
+                    help="extra FINGER code variants (code[:pf|:nopf]) on the spectrum leg")
     ap.add_argument("--mips", action="store_true",
                     help="also report both modes under the inner-product metric (FINGER_IP) on the "
                          "same points and graph, against inner-product ground truth")
@@ -420,6 +422,21 @@ def main() -> int:
                             screened=round(th["screened"], 1), skipped=round(th["skipped"], 1),
                             alg_gbs=round(th["alg_gbs"], 1),
                             hbm_frac=round(th["alg_gbs"] / PEAK_HBM_GBS, 4), launch=th["launch"])
+        for variant in [c for c in a.spectrum_codes.split(",") if c]:
+            code, _, pfs = variant.partition(":")
+            pf = {"pf": 1, "nopf": -1, "": 0}[pfs]
+            tv = api.finger_build_tables(dd2, dG2, rank=a.rank, code_type=code_of[code][0], pivots=piv2,
+                                         seed=0)
+            sw, op = sweep(tv, L.MODE_FINGER, prefetch=pf, gt=gt2, queries=dq2)
+            th = timed(tv, L.MODE_FINGER, op["ef"], a.steps, a.warmup, code_of[code][1], code == "fp8",
+                       prefetch=pf, gt=gt2, queries=dq2, rank=a.rank)
+            log(f"finger {variant} timed (c2s): {th}")
+            sift[f"finger_r64_{variant}"] = dict(
+                ef=op["ef"], recall=round(th["recall"], 4), qps=round(th["qps"], 1),
+                kernel_ms=round(th["kernel_ms"], 4), exact=round(th["exact"], 1),
+                alg_gbs=round(th["alg_gbs"], 1), launch=th["launch"],
+                speedup_vs_plain=round(th["qps"] / sift["plain"]["qps"], 4))
+            tv.close()
         sift["speedup_r64_vs_plain"] = round(sift["finger_r64"]["qps"] / sift["plain"]["qps"], 4)
         sift["speedup_r16_vs_plain"] = round(sift["finger_r16"]["qps"] / sift["plain"]["qps"], 4)
         t64.close()
