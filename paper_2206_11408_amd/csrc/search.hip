@@ -535,7 +535,11 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       // 2. one round trip: adjacency (+ screening inputs)
       int nb = -1;
       if (l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
-      float al = 0.f, rh = 0.f, ccv = 0.f, pc0 = 0.f;
+      float al = 0.f, rh = 0.f, ccv = 0.f;
+      // P c of the centre, element l + 64 t in pcv[t] (rpad <= 256), read in
+      // this round trip so that forming w below waits on no memory access
+      // (a wait there would also drain the code loads issued before it)
+      float pcv[4] = {0.f, 0.f, 0.f, 0.f};
       if constexpr (MODE != FINGER_MODE_PLAIN) {
         if (screening) {
           if (csub < a.deg) {
@@ -545,7 +549,9 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
               code.load(a.codes, ((int64_t)cur * a.deg + csub) * a.rpad + ch * kChunk);
           }
           ccv = a.cc[cur];
-          if (l < a.rpad) pc0 = a.pc[(int64_t)cur * a.rpad + l];
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (l + 64 * t < a.rpad) pcv[t] = a.pc[(int64_t)cur * a.rpad + l + 64 * t];
         }
       }
       // 3. visited test-and-set
@@ -579,11 +585,14 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           const float rq2 = fmaxf(qq - aq * qc, 0.f);
           const float rq = sqrtf(rq2);
           float w2 = 0.f;
-          for (int i = l; i < a.rpad; i += 64) {
-            const float pc = i < 64 ? pc0 : a.pc[(int64_t)cur * a.rpad + i];
-            const float w = pqv[i] - aq * pc;
-            wv[i] = w;
-            w2 += w * w;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i = l + 64 * t;
+            if (i < a.rpad) {
+              const float w = pqv[i] - aq * pcv[t];
+              wv[i] = w;
+              w2 += w * w;
+            }
           }
           w2 = wave_sum(w2);
           const float inv_w = w2 > 0.f ? 1.0f / sqrtf(w2) : 0.f;
