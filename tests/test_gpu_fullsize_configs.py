@@ -16,7 +16,7 @@ overflow); 48 sampled queries are re-searched by the oracle with the same
 quantized codes and must match wherever their screening margin exceeds
 1e-4 (at least 8 of them must).
 
-Building these takes minutes (the 10M-point graph alone about seven), so the
+Building these takes minutes (the 10M-point graph alone about five), so the
 module runs only with FINGER_FULLSIZE_CONFIGS=1."""
 import os
 import sys
