@@ -126,7 +126,8 @@ def main() -> int:
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the per-shard search on a "
-              "single MI355X (see DESIGN.md for how it would shard). Use --gpus 1.",
+              "single MI355X; the index would be sharded by queries or by data across GPUs, "
+              "which is not run here. Use --gpus 1.",
               file=sys.stderr)
         return 2
 
