@@ -125,7 +125,7 @@ def main() -> int:
     a = ap.parse_args()
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the per-shard search on a "
+        print("bench.py measures one GPU only: it runs the per-shard search on a "
               "single MI355X; the index would be sharded by queries or by data across GPUs, "
               "which is not run here. Use --gpus 1.",
               file=sys.stderr)
