@@ -95,3 +95,16 @@ def test_argument_errors(api):
         args = dict(knn_k=3, max_degree=4, entry=0) | kw
         with pytest.raises(L.FingerError):
             api.finger_build_graph(data, **args)
+
+
+def test_exact_duplicates_match_oracle(api):
+    """Every point three times: distance-0 ties decide the kNN (the point
+    itself excluded, its copies kept, ordered by id), the symmetrized rows
+    and the heuristic's strict comparison (a candidate at distance 0 from a
+    kept copy is dropped)."""
+    rng = np.random.default_rng(9)
+    base = rng.integers(0, 16, size=(400, 8)).astype(np.float32)
+    data = np.ascontiguousarray(np.repeat(base, 3, axis=0)[rng.permutation(1200)])
+    G, st = api.finger_build_graph(_t(data), knn_k=6, max_degree=8, entry=0)
+    O, ost = og.build(data, 6, 8, 0)
+    _compare(G.cpu().numpy(), st, O, ost, "exact duplicates 1200 x 8", exact=True)
