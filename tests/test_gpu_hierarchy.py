@@ -141,3 +141,46 @@ def test_attach_and_entry_errors(api):
     api.finger_hierarchy_attach(tab, levels, upper)
     ent, _ = api.finger_descend(tab, _t(qs[:4]))
     assert (ent.cpu().numpy() >= 0).all()
+
+
+def test_angular_search_from_descent_matches_oracle(api):
+    """Angular tables: the library normalizes the queries before the descent
+    and the search; the oracle runs both on the unit vectors."""
+    from paper_2206_11408_amd import _lib as L
+    data, qs, G, levels, upper, top = _hier("c1")
+    tab = api.finger_build_tables(_t(data), _t(G), rank=0, metric=L.ANGULAR)
+    api.finger_hierarchy_attach(tab, levels, upper)
+    ids, dist, ctr = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), mode=0, k=10, ef=32,
+                                                                  entry=L.ENTRY_DESCENT))
+    sd, sq = normalize_rows(data), normalize_rows(qs)
+    oe, _ = hierarchy_entries(sq, sd, levels, upper)
+    oi, od, oc, _ = search_batch(sd, G, sq, oe, 32, 10)
+    same = (ids == oi).all(1)
+    _say(f"angular plain search from descent entries: identical on {same.mean():.4f}")
+    assert same.mean() >= 0.99
+    np.testing.assert_array_equal(ctr[same][:, :6], oc[same])
+
+
+def test_persistent_mixed_batch_from_descent(api):
+    """One persistent launch, per-query K and ef, descent entries: equal to
+    per-group launches and to the oracle on integer data."""
+    import torch
+    from paper_2206_11408_amd import _lib as L
+    data, qs, G, levels, upper, top = _hier("c2")
+    tab = api.finger_build_tables(_t(data), _t(G), rank=32, seed=0)
+    api.finger_hierarchy_attach(tab, levels, upper)
+    rng = np.random.default_rng(6)
+    nq = qs.shape[0]
+    K = rng.choice([1, 10, 20], size=nq).astype(np.int32)
+    EF = rng.choice([16, 32, 64], size=nq).astype(np.int32)
+    p = api.search_params(mode=0, k=20, k_max=20, ef=16, entry=L.ENTRY_DESCENT,
+                          k_per_query=torch.as_tensor(K, device="cuda"),
+                          ef_per_query=torch.as_tensor(EF, device="cuda"), ef_max=64, persistent=1)
+    ids, dist, ctr = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), p))
+    oe, _ = hierarchy_entries(qs.astype(np.float64), data.astype(np.float64), levels, upper)
+    oi, od, oc, _ = search_batch(data, G, qs, oe, EF, K)
+    for i in range(nq):
+        np.testing.assert_array_equal(ids[i, :K[i]], oi[i, :K[i]])
+        assert (ids[i, K[i]:] == -1).all()
+    np.testing.assert_array_equal(ctr[:, :6], oc)
+    _say("persistent mixed batch from descent entries: bit-exact on every query")
