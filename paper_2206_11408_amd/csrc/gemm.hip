@@ -429,13 +429,16 @@ hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float*
 
 namespace {
 
-constexpr int kKnnSlack = 32;
+// candidates kept beyond k for the exact re-rank: a true neighbour is lost
+// only if 16 others sit within the split-precision score error (about 1e-5
+// relative) of it; integer data up to 256 scores exactly
+constexpr int kKnnSlack = 16;
 
 // Candidate scores for the kNN on the bf16 matrix cores, in split precision:
 // each float x is staged as hi = bf16(x) and lo = bf16(x - hi), and
 // A.B ~ hi.hi' + hi.lo' + lo.hi' (the dropped lo.lo' term is below 2^-16 of
 // |x||y|), accumulated in float32 by v_mfma_f32_16x16x32_bf16.  The scores
-// only choose the k + 32 candidates that k_knn_final re-ranks by exact
+// only choose the k + kKnnSlack candidates that k_knn_final re-ranks by exact
 // float32 differences.  LDS: hi/lo tiles of A and B, 64 rows x 32 k, rows
 // padded to 40 elements (80 bytes) so a lane's 16-byte fragment read stays
 // aligned.
