@@ -521,11 +521,13 @@ __device__ __forceinline__ void tile_mma_x3(const float* __restrict__ A, int64_t
 }
 
 // Each block: 64 queries x a contiguous range of data columns.  The running
-// best KK (approximate d2, id) per query live in LDS as sorted lists.
-__global__ void __launch_bounds__(256) k_knn_tiles(const float* Q, int64_t nq, const float* X,
-                                                   int64_t n, int K, const float* qn,
-                                                   const float* xn, int KK, int64_t chunk,
-                                                   uint64_t* out, int nchunks, int ip) {
+// best KK (approximate d2, id) per query live in LDS as sorted lists.  The
+// tile loop waits on LDS and on the global loads of the next tile, so
+// occupancy pays: registers are capped so that four waves share a SIMD (the
+// LDS lists admit four blocks per CU in any case).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_knn_tiles(const float* Q, int64_t nq, const float* X, int64_t n, int K, const float* qn,
+            const float* xn, int KK, int64_t chunk, uint64_t* out, int nchunks, int ip) {
   extern __shared__ __align__(16) char smem[];
   __bf16* S = reinterpret_cast<__bf16*>(smem);
   uint64_t* lists = reinterpret_cast<uint64_t*>(smem + kX3Bytes);
