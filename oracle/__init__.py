@@ -7,7 +7,8 @@ in ``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` use it.  It
 shares no code with the HIP library; the only thing both sides consume is
 the seeded inputs from ``workloads``.
 
-Everything here is plain, slow, single-threaded NumPy in float64:
+Everything here is plain, slow, single-threaded float64 (NumPy, and one
+C file):
 
 * ``knn``       exact distances and brute-force kNN, recall@K (Section 1).
 * ``rng``       the counter-based generator used to draw build samples.
@@ -17,6 +18,9 @@ Everything here is plain, slow, single-threaded NumPy in float64:
                 written from the definitions, not from the factorized tables.
 * ``search``    greedy graph search (Algorithm 1) and approximate greedy
                 search (Algorithm 4, Supplementary C).
+* ``csearch``   the same two searches compiled as plain C (``csearch.c``),
+                for timing the host's cores; cross-checked against
+                ``search`` by the tests.
 * ``codes``     BF16 / OCP FP8-E4M3 rounding of edge codes (extension; not in
                 the paper).
 * ``mlp``       the skip-gate network: forward, backward, Adam (extension).
