@@ -111,6 +111,9 @@ def main() -> int:
                          "decaying noise spectrum calibrated to the paper's SIFT rank")
     ap.add_argument("--spectrum-codes", default="",
                     help="extra FINGER code variants (code[:pf|:nopf]) on the spectrum leg")
+    ap.add_argument("--wide", default="",
+                    help="comma-separated 1M x 960 workloads (c3a: isotropic noise, c3s: decaying "
+                         "spectrum) on which to also measure plain and FINGER (bf16 and fp8 codes)")
     ap.add_argument("--mips", action="store_true",
                     help="also report both modes under the inner-product metric (FINGER_IP) on the "
                          "same points and graph, against inner-product ground truth")
@@ -201,9 +204,9 @@ def main() -> int:
             p.kernel_events[1] = kev[1].cuda_event
         return api.finger_search(tab, d_q if queries is None else queries, p, out=out)
 
-    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT, gt=None, queries=None):
+    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT, gt=None, queries=None, efs=EF_SWEEP):
         res = []
-        for ef in EF_SWEEP:
+        for ef in efs:
             run(tab, mode, ef, prefetch=prefetch, entry=entry, queries=queries)
             torch.cuda.synchronize()
             ev[0].record()
@@ -226,7 +229,7 @@ def main() -> int:
         return res, (min(ok, key=lambda r: r["ef"]) if ok else max(res, key=lambda r: r["recall"]))
 
     def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0, entry=L.ENTRY_PIVOT, gt=None,
-              queries=None, rank=None):
+              queries=None, rank=None, m=None):
         nq = a.nq
         d_q = d_q_main if queries is None else queries
         out = (torch.empty((nq, 10), dtype=torch.int32, device=dev),
@@ -295,7 +298,7 @@ def main() -> int:
             graph_step = (time.perf_counter() - g0) / steps
             del cg
         ids, dist, ctr = (x.cpu().numpy() for x in out)
-        B = algorithmic_bytes(ctr, spec.m, spec.max_degree, (a.rank if rank is None else rank) if mode else 0,
+        B = algorithmic_bytes(ctr, spec.m if m is None else m, spec.max_degree, (a.rank if rank is None else rank) if mode else 0,
                               code_bytes, 10, fp8)
         kavg = float(np.mean(kms))
         if graph_step is not None:
@@ -443,6 +446,56 @@ def main() -> int:
         t64.close()
         t16.close()
         del dd2, dq2, dG2
+
+    wide = {}
+    for wname in [w for w in a.wide.split(",") if w]:
+        # a 960-d workload (GIST-1M-960's shape): a vector is 3,840 bytes
+        # against 136 (bf16) or 72 (fp8) bytes per edge code at r = 64, the
+        # regime where screening can pay in bytes if the residuals are low-rank
+        spec3 = SPECS[wname].scaled(nq=a.nq)
+        t0 = time.time()
+        data3, q3 = make_points(spec3)
+        dd3 = torch.as_tensor(data3, device=dev)
+        dq3 = torch.as_tensor(q3, device=dev)
+        log(f"{wname} points n={spec3.n} m={spec3.m} in {time.time() - t0:.1f}s")
+        t0 = time.time()
+        dG3, gst3 = api.finger_build_graph(dd3, knn_k=spec3.knn_k, max_degree=spec3.max_degree,
+                                           entry=medoid(data3))
+        torch.cuda.synchronize()
+        log(f"{wname} graph in {time.time() - t0:.1f}s: {gst3}")
+        piv3 = pick_pivots(spec3.n, a.pivots, spec3.seed)
+        gi3, gd3 = api.finger_exact_knn(dd3, dq3, 10)
+        gt3 = (gi3.cpu().numpy(), gd3.cpu().numpy())
+        noise = f"noise spectrum i^-{spec3.decay}" if spec3.decay > 0 else "isotropic noise"
+        res = {"workload": (f"{wname}: n={spec3.n} m={spec3.m} float32, {spec3.n_centers} uniform centres + "
+                            f"{spec3.sigma} Gaussian {noise}, 16-NN sym pruned deg 32, {a.pivots} pivots, "
+                            f"nq={a.nq}, K=10")}
+        efs3 = EF_SWEEP + (256, 320, 400)
+        for rank in (a.rank, 16):
+            for code in ("bf16", "fp8"):
+                tw = api.finger_build_tables(dd3, dG3, rank=rank, code_type=code_of[code][0], pivots=piv3,
+                                             seed=0)
+                res[f"corr_xy_r{rank}"] = round(tw.info()["corr_xy"], 4)
+                legs = [(f"finger_{code}_r{rank}", L.MODE_FINGER)]
+                if code == "bf16" and rank == a.rank:
+                    legs.insert(0, ("plain", L.MODE_PLAIN))   # plain reads no codes
+                for nm, mode in legs:
+                    log(f"sweep {nm} ({wname})")
+                    sw, op = sweep(tw, mode, gt=gt3, queries=dq3, efs=efs3)
+                    th = timed(tw, mode, op["ef"], a.steps, a.warmup, code_of[code][1], code == "fp8",
+                               gt=gt3, queries=dq3, rank=rank, m=spec3.m)
+                    log(f"{nm} timed ({wname}): {th}")
+                    res[nm] = dict(ef=op["ef"], recall=round(th["recall"], 4), qps=round(th["qps"], 1),
+                                   kernel_ms=round(th["kernel_ms"], 4), exact=round(th["exact"], 1),
+                                   screened=round(th["screened"], 1), skipped=round(th["skipped"], 1),
+                                   alg_gbs=round(th["alg_gbs"], 1),
+                                   hbm_frac=round(th["alg_gbs"] / PEAK_HBM_GBS, 4), launch=th["launch"])
+                    if mode == L.MODE_FINGER:
+                        res[nm]["speedup_vs_plain"] = round(th["qps"] / res["plain"]["qps"], 4)
+                tw.close()
+        wide[wname] = res
+        del dd3, dq3, dG3
+        torch.cuda.empty_cache()
 
     hier = None
     if a.hierarchy:
@@ -637,6 +690,8 @@ def main() -> int:
         line["inner_product"] = mips
     if sift:
         line["sift_like_spectrum"] = sift
+    if wide:
+        line["wide_960"] = wide
     if a.oracle_legs:
         # graph construction at a size the float64 oracle finishes: the first
         # 20,000 points, same recipe, GPU and oracle side by side

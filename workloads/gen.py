@@ -63,6 +63,10 @@ SPECS = {
     # precision workloads
     "c3a": WorkloadSpec("c3a", "uniform", 1_000_000, 960, 1_000, 0.1, 10_000, seed=0),
     "c3b": WorkloadSpec("c3b", "heavy", 1_200_000, 100, 1_000, 1.0, 10_000, seed=0),
+    # c3a with a decaying noise spectrum, calibrated so that the rank rule of
+    # thumb (corr(X, Y) >= 0.7, r from 8 in steps of 8) settles on r = 16, the
+    # rank the paper's rule gives GIST-1M-960
+    "c3s": WorkloadSpec("c3s", "uniform", 1_000_000, 960, 1_000, 0.1, 10_000, seed=0, decay=0.4),
     # batching workload
     "c4": WorkloadSpec("c4", "gauss", 10_000_000, 96, 10_000, 0.5, 100_000, seed=0),
 }
