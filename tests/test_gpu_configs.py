@@ -2,7 +2,9 @@
 (the same points per cluster, dimension, rank, code format and K/ef mix as
 the full configurations):
 
-* 960-d clustered points, r = 64, BF16 and FP8 edge codes (L2);
+* 960-d clustered points, r = 64, BF16 and FP8 edge codes (L2), with
+  isotropic noise and with the GIST-calibrated decaying spectrum (where
+  FINGER skips about three quarters of the neighbours it screens);
 * 100-d heavy-tailed points under the angular metric, r = 64, BF16 and FP8;
 * 96-d clustered points, r = 32, FP8 codes, one persistent launch over
   queries with K drawn from {1, 10, 100} and ef from {32, 64, 128, 256, 512}.
@@ -57,8 +59,8 @@ def _workload(name):
     """(raw data, raw queries, search-space data, search-space queries, graph, pivots)."""
     if name in _CACHE:
         return _CACHE[name]
-    if name == "c3a":
-        spec = SPECS["c3a"].scaled(n=20_000, n_centers=20, nq=48)
+    if name in ("c3a", "c3s"):
+        spec = SPECS[name].scaled(n=20_000, n_centers=20, nq=48)
         npiv = 80
     elif name == "c3b":
         spec = SPECS["c3b"].scaled(n=24_000, n_centers=20, nq=48)
@@ -119,7 +121,8 @@ def _compare(ids, ctr, oi, oc, margin, label, thr=1e-4):
     np.testing.assert_array_equal(ctr[safe][:, :6], oc[safe])
 
 
-@pytest.mark.parametrize("name,code", [("c3a", "bf16"), ("c3a", "fp8"), ("c3b", "bf16"), ("c3b", "fp8")])
+@pytest.mark.parametrize("name,code", [("c3a", "bf16"), ("c3a", "fp8"), ("c3s", "bf16"), ("c3s", "fp8"),
+                                       ("c3b", "bf16"), ("c3b", "fp8")])
 def test_precision_workloads_search_parity(api, name, code):
     from paper_2206_11408_amd import _lib as L
     _say(f"{name} {code}: FINGER search with quantized codes vs oracle")
