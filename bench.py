@@ -111,9 +111,12 @@ def main() -> int:
                          "decaying noise spectrum calibrated to the paper's SIFT rank")
     ap.add_argument("--spectrum-codes", default="",
                     help="extra FINGER code variants (code[:pf|:nopf]) on the spectrum leg")
-    ap.add_argument("--wide", default="",
+    ap.add_argument("--wide", default="c3s",
                     help="comma-separated 1M x 960 workloads (c3a: isotropic noise, c3s: decaying "
-                         "spectrum) on which to also measure plain and FINGER (bf16 and fp8 codes)")
+                         "spectrum) on which to also measure plain and FINGER (bf16 and fp8 codes); "
+                         "empty to skip")
+    ap.add_argument("--wide-rule-rank", action="store_true",
+                    help="on the 960-d workloads also measure FINGER at r = 16 (the rank rule's choice)")
     ap.add_argument("--mips", action="store_true",
                     help="also report both modes under the inner-product metric (FINGER_IP) on the "
                          "same points and graph, against inner-product ground truth")
@@ -471,7 +474,7 @@ def main() -> int:
                             f"{spec3.sigma} Gaussian {noise}, 16-NN sym pruned deg 32, {a.pivots} pivots, "
                             f"nq={a.nq}, K=10")}
         efs3 = EF_SWEEP + (256, 320, 400)
-        for rank in (a.rank, 16):
+        for rank in (a.rank, 16) if a.wide_rule_rank else (a.rank,):
             for code in ("bf16", "fp8"):
                 tw = api.finger_build_tables(dd3, dG3, rank=rank, code_type=code_of[code][0], pivots=piv3,
                                              seed=0)
