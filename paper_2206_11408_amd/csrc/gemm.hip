@@ -146,6 +146,7 @@ constexpr int kPivKeep = 4;                      // candidates kept per query an
 constexpr int kPivCand = kPivKeep * kPivSplit;   // candidates per query (= 64, one per lane)
 constexpr int kPivRerank = 16;            // candidates re-ranked exactly
 constexpr int kPivKs = 8;                 // 32-wide k-steps of a query held in registers
+constexpr int kPivGroup = 4;              // pivot tiles sharing one chunk of query fragments
 constexpr int kPivTiles = 2;              // 16-row query tiles per wave
 constexpr int kPivRows = 16 * kPivTiles;  // queries per wave
 
@@ -274,23 +275,49 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
       for (int u = 0; u < NT; ++u) fold_tile(c[u], c_beg + t + 16 + lr, npiv, py, best[u]);
     }
   } else {
-    // long vectors: the query fragments are re-read (cached) per pivot tile
+    // long vectors: the k dimension is walked in chunks of kPivKs steps whose
+    // query fragments stay in registers across a group of kPivGroup pivot
+    // tiles, so each fragment is loaded and rounded once per group instead
+    // of once per tile; every tile still accumulates its k-steps in
+    // ascending order
+    constexpr int TG = kPivGroup;
     const int ksteps = kpad / 32;
-    for (int t = 0; t < range; t += 16) {
-      f4v c[NT];
+    const int ntile = range / 16;
+    for (int t0 = 0; t0 < ntile; t0 += TG) {
+      f4v c[TG][NT];
 #pragma unroll
-      for (int u = 0; u < NT; ++u) c[u] = f4v{0.f, 0.f, 0.f, 0.f};
-      for (int ks = 0; ks < ksteps; ++ks) {
-        const b8v b = *reinterpret_cast<const b8v*>(PB + (int64_t)(c_beg + t + lr) * kpad + 32 * ks + lk);
+      for (int g = 0; g < TG; ++g)
 #pragma unroll
-        for (int u = 0; u < NT; ++u)
-          c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              load_query_frag(Q, nq, m, q0 + 16 * u + lr, 32 * ks + lk), b, c[u], 0, 0, 0);
+        for (int u = 0; u < NT; ++u) c[g][u] = f4v{0.f, 0.f, 0.f, 0.f};
+      for (int k0 = 0; k0 < ksteps; k0 += kPivKs) {
+        b8v a[NT][kPivKs];
+#pragma unroll
+        for (int i = 0; i < kPivKs; ++i)
+#pragma unroll
+          for (int u = 0; u < NT; ++u)
+            if (k0 + i < ksteps) a[u][i] = load_query_frag(Q, nq, m, q0 + 16 * u + lr, 32 * (k0 + i) + lk);
+#pragma unroll
+        for (int g = 0; g < TG; ++g) {
+          if (t0 + g >= ntile) break;
+          const __bf16* brow = PB + (int64_t)(c_beg + 16 * (t0 + g) + lr) * kpad + lk;
+#pragma unroll
+          for (int i = 0; i < kPivKs; ++i) {
+            if (k0 + i >= ksteps) break;
+            const b8v b = *reinterpret_cast<const b8v*>(brow + 32 * (k0 + i));
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+              c[g][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], b, c[g][u], 0, 0, 0);
+          }
+        }
       }
-      const int col = c_beg + t + lr;
-      const float pn = pnorm[col];
 #pragma unroll
-      for (int u = 0; u < NT; ++u) fold_tile(c[u], col, npiv, pn, best[u]);
+      for (int g = 0; g < TG; ++g) {
+        if (t0 + g >= ntile) break;
+        const int col = c_beg + 16 * (t0 + g) + lr;
+        const float pn = pnorm[col];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) fold_tile(c[g][u], col, npiv, pn, best[u]);
+      }
     }
   }
 #pragma unroll
