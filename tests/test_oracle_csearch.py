@@ -127,3 +127,20 @@ def test_invalid_entry_is_an_error(small):
     data, qs, G, _ = small
     with pytest.raises(RuntimeError):
         csearch.search_batch(data, G, qs[:2], data.shape[0], 24, 10)
+
+
+def test_agrees_on_the_timed_configuration():
+    """The CPU baseline's configuration at reduced n: integer 128-d points,
+    per-query nearest-pivot entries, r = 64, FINGER at ef = 56."""
+    from oracle.search import pivot_entries
+    from tests import helpers
+    data, qs, G, _, piv = helpers.c2_small()
+    X, Q = data.astype(np.float64), qs.astype(np.float64)
+    tab = build(X, G, 64, n_samples=100_000, seed=0)
+    ent = pivot_entries(Q, X, piv)
+    a = search_batch(X, G, Q, ent, 56, 10, mode="finger", tables=tab)
+    b = csearch.search_batch(X, G, Q, ent, 56, 10, mode="finger", tables=tab, threads=4)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])    # integer data: exact squared distances
+    np.testing.assert_array_equal(a[2], b[2])
+    assert b[2][:, 3].sum() > 0
