@@ -474,7 +474,7 @@ def main() -> int:
                             f"{spec3.sigma} Gaussian {noise}, 16-NN sym pruned deg 32, {a.pivots} pivots, "
                             f"nq={a.nq}, K=10")}
         efs3 = EF_SWEEP + (256, 320, 400)
-        for rank in (a.rank, 16) if a.wide_rule_rank else (a.rank,):
+        for rank in (a.rank, 16) if a.wide_rule_rank and a.rank != 16 else (a.rank,):
             for code in ("bf16", "fp8"):
                 tw = api.finger_build_tables(dd3, dG3, rank=rank, code_type=code_of[code][0], pivots=piv3,
                                              seed=0)
