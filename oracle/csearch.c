@@ -131,9 +131,9 @@ static void admit(TopList* T, double d2, int64_t id) {
 }
 
 /* One query.  visit[] holds a stamp per node; ids equal to stamp are
- * visited.  Returns 0, or -1 on an invalid entry. */
+ * visited.  Returns 0, or -1 on an invalid entry or neighbour id. */
 static int search_one(const double* data, int64_t n, int m, const int32_t* graph, int deg,
-                      const double* q, int64_t entry, int ef_eff, int k, int mode, int metric,
+                      const double* q, int64_t entry, int k, int mode, int metric,
                       int warmup, const Tables* tab, uint32_t* visit, uint32_t stamp,
                       TopList* T, int64_t* nbuf, double* work, int64_t* out_ids, double* out_d2,
                       int64_t* cnt, double* margin) {
@@ -155,6 +155,7 @@ static int search_one(const double* data, int64_t n, int m, const int32_t* graph
     int nn = 0;
     for (int s = 0; s < deg; ++s) {
       const int64_t nb = graph[cur * deg + s];
+      if (nb >= n) return -1;
       if (nb < 0 || visit[nb] == stamp) continue;
       visit[nb] = stamp;
       ++visited;
@@ -217,14 +218,15 @@ int oracle_search_batch(const double* data, int64_t n, int32_t m, const int32_t*
   }
   const int ef_eff = ef > k ? ef : k;
   uint32_t* visit = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
-  TopList T = {(double*)malloc(sizeof(double) * ef_eff), (int64_t*)malloc(sizeof(int64_t) * ef_eff),
+  TopList T = {(double*)malloc(sizeof(double) * (size_t)ef_eff),
+               (int64_t*)malloc(sizeof(int64_t) * (size_t)ef_eff),
                (unsigned char*)malloc((size_t)ef_eff), 0, ef_eff};
-  int64_t* nbuf = (int64_t*)malloc(sizeof(int64_t) * deg);
+  int64_t* nbuf = (int64_t*)malloc(sizeof(int64_t) * (size_t)deg);
   double* work = (double*)malloc(sizeof(double) * (2 * (size_t)m + 2 * (size_t)(r > 0 ? r : 1)));
   int rc = 0;
   if (!visit || !T.d || !T.id || !T.done || !nbuf || !work) rc = -2;
   for (int64_t i = 0; i < nq && rc == 0; ++i)
-    rc = search_one(data, n, m, graph, deg, queries + i * m, entries[i], ef_eff, k, mode, metric,
+    rc = search_one(data, n, m, graph, deg, queries + i * m, entries[i], k, mode, metric,
                     warmup, &tab, visit, (uint32_t)(i + 1), &T, nbuf, work, out_ids + i * k,
                     out_d2 + i * k, out_counters + i * C_COUNT, out_margin + i);
   free(visit);

@@ -144,3 +144,10 @@ def test_agrees_on_the_timed_configuration():
     np.testing.assert_array_equal(a[1], b[1])    # integer data: exact squared distances
     np.testing.assert_array_equal(a[2], b[2])
     assert b[2][:, 3].sum() > 0
+
+
+def test_neighbour_id_out_of_range_is_an_error():
+    data = np.arange(3, dtype=np.float64)[:, None]
+    G = np.array([[1], [7], [1]], dtype=np.int32)
+    with pytest.raises(RuntimeError):
+        csearch.search_batch(data, G, np.array([[0.0]]), 0, 4, 2)
