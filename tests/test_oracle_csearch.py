@@ -151,3 +151,24 @@ def test_neighbour_id_out_of_range_is_an_error():
     G = np.array([[1], [7], [1]], dtype=np.int32)
     with pytest.raises(RuntimeError):
         csearch.search_batch(data, G, np.array([[0.0]]), 0, 4, 2)
+
+
+def _finger_traces():
+    with open(os.path.join(GOLD, "finger_traces.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _finger_traces(), ids=lambda c: c["name"])
+@pytest.mark.parametrize("which", ["numpy", "compiled"])
+def test_hand_traced_finger_search(case, which):
+    data = np.array(case["points"], dtype=np.float64)
+    G = np.array(case["graph"], dtype=np.int32)
+    q = np.array([case["query"]], dtype=np.float64)
+    tab = identity_dm({"P": np.eye(data.shape[1])})
+    run = search_batch if which == "numpy" else csearch.search_batch
+    ids, d2, cnt, _ = run(data, G, q, case["entry"], case["ef"], case["k"], mode="finger",
+                          tables=tab, warmup=case["warmup"])
+    assert ids[0].tolist() == case["expect_ids"]
+    np.testing.assert_allclose(d2[0], case["expect_d2"], rtol=1e-12, atol=1e-12)
+    for kname, v in case["expect_counters"].items():
+        assert cnt[0, COUNTERS.index(kname)] == v, kname
