@@ -224,7 +224,7 @@ typedef struct finger_search_params {
                             descent through the attached upper layers ends
                             (finger_hierarchy_attach, finger_descend) */
   int32_t warmup;        /* W: screening starts once more than W nodes have
-                            been expanded (Algorithm 4's "> 5 updates"); < 0 = 5 */
+                            been expanded (Algorithm 4's warm-up); < 0 = 5 */
   int32_t k_max;         /* row stride of out_ids/out_dist; >= every K */
   const int32_t* k_per_query;  /* device int32 [nq] or NULL */
   const int32_t* ef_per_query; /* device int32 [nq] or NULL */

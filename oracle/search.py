@@ -16,8 +16,9 @@ set.  Readings of the pseudo-code:
   then on, so Algorithm 1 would stop as soon as it became the nearest of C;
   hence "pop the nearest of C; stop if it is beyond ub" is the same as
   "expand the best unexpanded entry of T; stop when there is none".
-* Screening (Algorithm 4).  "#updates of cur > 5" is read as: the number
-  of expansions so far, counting the current one, exceeds W (default 5).
+* Screening (Algorithm 4).  Its warm-up condition is read as: screening
+  starts once the number of expansions so far, counting the current one,
+  exceeds W (default 5).
   The screen is applied only when T is full at the start of the expansion
   (otherwise every neighbour would be admitted anyway).  A screened-out
   neighbour stays in V.  Survivors get their exact distance and the normal

@@ -1,8 +1,8 @@
-"""The hand-traced run of Algorithm 4 (tests/golden/finger_traces.json) on
-the GPU kernel: the one-dimensional points padded with zeros to m = 4, the
-identity basis (r = m) and distribution matching switched off, so the
-kernel's factorized estimate is exact as well and every screening decision
-and counter must match the hand derivation."""
+"""The hand-traced runs of Algorithm 4 (tests/golden/finger_traces.json) on
+the GPU kernel: the points padded with zeros to m = 4, the identity basis
+(r = m) and each case's distribution-matching constants (the identity, or
+the hand-chosen affine maps of the three-dimensional cases), so every
+screening decision and counter must match the hand derivation."""
 import json
 import os
 import sys
@@ -37,7 +37,8 @@ def test_hand_traced_finger_search_on_gpu(case):
     G = np.array(case["graph"], dtype=np.int32)
     assert G.shape[0] == data.shape[0] and G.max() < data.shape[0]
     tab = api.finger_build_tables(torch.as_tensor(data, device="cuda"), torch.as_tensor(G, device="cuda"),
-                                  rank=m, seed=0, basis=np.eye(m), dm_override=(0, 1, 0, 1, 0))
+                                  rank=m, seed=0, basis=np.eye(m),
+                                  dm_override=tuple(case.get("dm", (0, 1, 0, 1, 0))))
     ids, d2, ctr = (x.cpu().numpy() for x in api.finger_search(
         tab, torch.as_tensor(q, device="cuda"), mode=1, k=case["k"], ef=case["ef"],
         entry=case["entry"], warmup=case["warmup"]))

@@ -165,6 +165,8 @@ def test_hand_traced_finger_search(case, which):
     G = np.array(case["graph"], dtype=np.int32)
     q = np.array([case["query"]], dtype=np.float64)
     tab = identity_dm({"P": np.eye(data.shape[1])})
+    if "dm" in case:
+        tab.update(zip(("mu", "sigma", "mu_hat", "sigma_hat", "eps"), map(float, case["dm"])))
     run = search_batch if which == "numpy" else csearch.search_batch
     ids, d2, cnt, _ = run(data, G, q, case["entry"], case["ef"], case["k"], mode="finger",
                           tables=tab, warmup=case["warmup"])
