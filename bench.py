@@ -126,6 +126,8 @@ def main() -> int:
     ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=False,
                     help="time the step as a replay of a captured HIP graph (kernel times "
                          "still come from the eager launches)")
+    ap.add_argument("--screen-layout", type=int, default=0, choices=(0, 1, 2),
+                    help="FINGER screen: 0 library default, 1 coalesced, 2 per-lane chunks")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (the reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -201,11 +203,12 @@ def main() -> int:
     launch = {}   # (mode, code) -> tuned launch settings
 
     def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0, entry=L.ENTRY_PIVOT, queries=None):
-        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, code_prefetch=prefetch)
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, code_prefetch=prefetch,
+                              screen_layout=a.screen_layout)
         if time_kernel:
             p.kernel_events[0] = kev[0].cuda_event
             p.kernel_events[1] = kev[1].cuda_event
-        return api.finger_search(tab, d_q if queries is None else queries, p, out=out)
+        return api.finger_search(tab, d_q if queries is None else queries, p, out=out, check=False)
 
     def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT, gt=None, queries=None, efs=EF_SWEEP):
         res = []
@@ -218,6 +221,7 @@ def main() -> int:
             torch.cuda.synchronize()
             ms = ev[0].elapsed_time(ev[1])
             rc = recall(ids.cpu().numpy(), dist.cpu().numpy(), gt)
+            api.check_status(ctr)
             c = ctr.cpu().numpy()
             res.append(dict(ef=ef, recall=rc, ms=ms, qps=a.nq / ms * 1e3,
                             exact=float(c[:, 1].mean()), screened=float(c[:, 2].mean()),
@@ -239,7 +243,7 @@ def main() -> int:
                torch.empty((nq, 10), dtype=torch.float32, device=dev),
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
         if a.tune:
-            base = dict(mode=mode, k=10, ef=ef, entry=entry)
+            base = dict(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout)
             ch = tune.autotune(tab, d_q, base, repeats=3, cache_path=None, log=log)
             if prefetch != 0:   # an explicitly requested code-prefetch setting stays fixed
                 best = min((t, c) for t, c in ch["all"] if c["code_prefetch"] == prefetch)[1]
@@ -249,13 +253,13 @@ def main() -> int:
                                                          "visited_capacity")}
             log(f"tuned launch mode={mode}: {launch[(mode, id(tab), prefetch, entry)]}")
         geo = launch.get((mode, id(tab), prefetch, entry), {})
-        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry,
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout,
                               code_prefetch=geo.get("code_prefetch", prefetch),
                               waves_per_cu=geo.get("waves_per_cu", 0),
                               persistent=geo.get("persistent", 0),
                               visited_capacity=geo.get("visited_capacity", 0))
         for _ in range(warmup):
-            api.finger_search(tab, d_q, p, out=out)
+            api.finger_search(tab, d_q, p, out=out, check=False)
         pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                  for _ in range(steps)]
         for e0, e1 in pairs:   # create the HIP events before the timed region
@@ -267,7 +271,7 @@ def main() -> int:
         for e0, e1 in pairs:
             p.kernel_events[0] = e0.cuda_event
             p.kernel_events[1] = e1.cuda_event
-            api.finger_search(tab, d_q, p, out=out)
+            api.finger_search(tab, d_q, p, out=out, check=False)
         ev[1].record()
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
@@ -277,7 +281,7 @@ def main() -> int:
         if a.graph:
             # the same step captured once in a HIP graph and replayed: query
             # preparation and search without per-launch host gaps
-            pg = api.search_params(mode=mode, k=10, ef=ef, entry=entry,
+            pg = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout,
                                    code_prefetch=geo.get("code_prefetch", prefetch),
                                    waves_per_cu=geo.get("waves_per_cu", 0),
                                    persistent=geo.get("persistent", 0),
@@ -285,12 +289,12 @@ def main() -> int:
             side = torch.cuda.Stream()
             side.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(side):
-                api.finger_search(tab, d_q, pg, out=out)
+                api.finger_search(tab, d_q, pg, out=out, check=False)
             torch.cuda.current_stream().wait_stream(side)
             torch.cuda.synchronize()
             cg = torch.cuda.CUDAGraph()
             with torch.cuda.graph(cg):
-                api.finger_search(tab, d_q, pg, out=out)
+                api.finger_search(tab, d_q, pg, out=out, check=False)
             for _ in range(warmup):
                 cg.replay()
             torch.cuda.synchronize()
@@ -300,6 +304,7 @@ def main() -> int:
             torch.cuda.synchronize()
             graph_step = (time.perf_counter() - g0) / steps
             del cg
+        api.check_status(out[2])   # after the timed region: no visited-set overflow
         ids, dist, ctr = (x.cpu().numpy() for x in out)
         B = algorithmic_bytes(ctr, spec.m if m is None else m, spec.max_degree, (a.rank if rank is None else rank) if mode else 0,
                               code_bytes, 10, fp8)
@@ -608,7 +613,19 @@ def main() -> int:
         from oracle import csearch
         X64 = np.ascontiguousarray(data, dtype=np.float64)
         Q64 = np.ascontiguousarray(qs, dtype=np.float64)
-        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+        # the GPU machine allots a share of 16 host cores to its one GPU (more
+        # threads would compete with the other tenants of the host), so the
+        # oracle runs on min(16, affinity) threads; the counts and the CPU
+        # model are recorded with the result
+        affinity = len(os.sched_getaffinity(0))
+        cores = max(1, min(16, affinity))
+        cpu_model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                                 "unknown")
+        except OSError:
+            pass
         n1 = min(a.cpu_sample, 1000)
         w0 = time.perf_counter()
         c1 = csearch.search_batch(X64, G, Q64[:n1], ent[:n1], op_f["ef"], 10, mode="finger", tables=orc)
@@ -621,6 +638,8 @@ def main() -> int:
                "sample": f"{a.cpu_sample} of the {a.nq} queries, FINGER mode at ef={op_f['ef']}, "
                          f"compiled float64 oracle search on {cores} threads over disjoint query "
                          f"ranges (entries and tables precomputed)",
+               "cpu_model": cpu_model, "os_cpu_count": os.cpu_count(), "affinity_cpus": affinity,
+               "cores_policy": "min(16, affinity): the GPU box's host share for one GPU",
                "single_thread_qps": round(c_single, 3),
                "numpy_oracle_one_core_qps": round(numpy_qps, 3),
                "numpy_oracle_sample": f"{a.cpu_sample} queries, entry selection included",

@@ -44,7 +44,8 @@ typedef enum {
   FINGER_EDEVICE = -3,    /* a HIP call failed; message has the HIP error */
   FINGER_ENODEV = -4,     /* no usable gfx950 device */
   FINGER_EOVERFLOW = -5,  /* a fixed capacity (LDS, table) cannot hold the request */
-  FINGER_EINTERNAL = -6
+  FINGER_EINTERNAL = -6,
+  FINGER_ECORRUPT = -7    /* a tables image fails its checksum or format checks */
 } finger_status;
 
 typedef enum {
@@ -86,10 +87,12 @@ enum {
   FINGER_CTR_SKIPPED = 3,    /* screened neighbours whose estimate exceeded ub */
   FINGER_CTR_VISITED = 4,    /* |V| at the end */
   FINGER_CTR_PREPS = 5,      /* expansions that screened (each reads c.c and P c) */
-  FINGER_CTR_STATUS = 6,     /* 0 = ok; bit 0: visited-set capacity reached (the
-                                remaining neighbours were treated as visited;
-                                raise visited_capacity); bit 1: ef_eff clipped
-                                to ef_max */
+  FINGER_CTR_STATUS = 6,     /* 0 = ok; bit 0: the visited set overflowed (its
+                                LDS table and its spill table were both full):
+                                the query's results are NOT valid, which is the
+                                asynchronous form of FINGER_EOVERFLOW (raise
+                                visited_capacity or spill_capacity and search
+                                again); bit 1: ef_eff clipped to ef_max */
   FINGER_NCOUNTERS = 7
 };
 
@@ -235,11 +238,25 @@ typedef struct finger_search_params {
   int32_t waves_per_cu;  /* resident query waves per CU; 0 = library default */
   int32_t visited_capacity; /* visited-set slots per query (power of two,
                                >= 256); 0 = default from ef_max */
+  int32_t spill_capacity; /* visited-set spill slots per resident query wave
+                             in the workspace (power of two, >= 64); 0 =
+                             default next_pow2(ef_max * max_degree) clamped
+                             to [1024, 65536].  Together with the LDS table
+                             it bounds |V| per query (status bit 0). */
   int32_t code_prefetch; /* FINGER mode: 1 = request every slot's edge code
                             together with the adjacency row (one round trip
                             fewer, more bytes); -1 = request codes of
                             unvisited neighbours only; 0 = library default
                             (prefetch for BF16/FP8 codes) */
+  int32_t screen_layout; /* FINGER mode: how lanes read the edge codes.
+                            0 = library default (coalesced where it applies);
+                            1 = coalesced: each load instruction reads 1 KB of
+                            the centre's contiguous code block, a lane holds
+                            one 16-byte piece of a slot's code (code rows of
+                            32..256 bytes and max_degree <= 32; other shapes
+                            fall back to 2); 2 = per-lane chunks: a lane holds
+                            32 consecutive elements of one slot's code.
+                            Results do not depend on it. */
   /* Gate-training log (mode FINGER only; NULL = off).  For every screened
    * neighbour the kernel appends one row of FINGER_GATE_FEATURES(r) floats
    * (see finger_gate_attach) to log_features, its exact squared distance
@@ -420,7 +437,7 @@ FINGER_API int finger_exact_knn_workspace_size(int64_t n, int32_t m, int64_t nq,
 /*
  * finger_exact_knn - brute-force K nearest neighbours (the ground truth A of
  * recall@K, Section 1).  Candidates are selected with an MFMA GEMM
- * (|q|^2 + |x|^2 - 2 q.x), the best K+32 per query are re-ranked by direct
+ * (|q|^2 + |x|^2 - 2 q.x), the best K+16 per query are re-ranked by direct
  * differences in float32 and returned sorted by (d2, id).  Async.
  *   data [n][m], queries [nq][m] float; out_ids int32 / out_dist float
  *   [nq][k].  k <= n, k <= 256.  FINGER_ANGULAR normalizes both sides.
@@ -477,18 +494,89 @@ FINGER_API int64_t finger_gate_param_count(int32_t in_dim, int32_t hidden);
  * Adam moments are float [P] in the layout above (device).
  *   finger_mlp_forward:  x [B][in] float -> y [B] float.
  *   finger_mlp_backward: loss = mean over the batch of (y - target)^2;
- *                        writes grad [P] (overwritten) and *loss (device float).
+ *                        writes grad [P] (overwritten) and *loss (device
+ *                        float, may be NULL).  Per-block partial gradients go
+ *                        to the caller's workspace of at least
+ *                        finger_mlp_backward_workspace_size bytes (256-byte
+ *                        aligned); the call allocates nothing.
  *   finger_adam_step:    Adam (Kingma & Ba) with bias correction at step t >= 1.
- * Async.  Errors: EINVAL (sizes, NULL pointers), EDEVICE.
+ * 1 <= in_dim <= 512, 1 <= hidden <= 64.  Async.  Errors: EINVAL (sizes,
+ * NULL pointers, workspace too small), EDEVICE.
  */
 FINGER_API int finger_mlp_forward(const float* weights, int32_t in_dim, int32_t hidden,
                        const float* x, int64_t batch, float* y, void* stream);
+FINGER_API int finger_mlp_backward_workspace_size(int32_t in_dim, int32_t hidden, int64_t batch,
+                                                  size_t* bytes /* host */);
 FINGER_API int finger_mlp_backward(const float* weights, int32_t in_dim, int32_t hidden,
                         const float* x, const float* target, int64_t batch,
-                        float* grad, float* loss, void* stream);
+                        float* grad, float* loss, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/*
+ * finger_gate_calibrate - the gate's correction term, the analogue of
+ * Algorithm 2's eps for the learned map: eps_gate = mean over the rows of
+ * |target - f(x)|, with f evaluated by the forward kernel and the mean
+ * accumulated in float64 in a fixed order (deterministic).  Typically the
+ * rows are a held-out part of a finger_search feature log and the targets
+ * come from finger_gate_targets.  Synchronous; allocates its scratch
+ * (rows floats plus a few KB) and frees it before returning.
+ * Errors: EINVAL (NULL pointers, rows < 1, sizes as above), ENOMEM, EDEVICE.
+ */
+FINGER_API int finger_gate_calibrate(const float* weights, int32_t in_dim, int32_t hidden,
+                                     const float* x, const float* target, int64_t rows,
+                                     double* eps_gate /* host */, void* stream);
 FINGER_API int finger_adam_step(float* weights, const float* grad, float* m1, float* m2,
                      int64_t count, float lr, float beta1, float beta2, float eps,
                      int32_t step, void* stream);
+
+/* ----------------------------------------------------------- checkpoint */
+
+/*
+ * The build costs minutes on the paper's CPU (Table 1, Supplementary F) and
+ * seconds here; a tables image lets a process skip it.
+ *
+ * finger_tables_export - write the handle's tables into one host image:
+ * a header (magic "FINGERTB", format version 1, n, m, r, max_degree, code
+ * type, metric, sigma mode, pivot count, build seed, the five
+ * distribution-matching constants, corr(X, Y), eps_gate, and checksums of
+ * the graph rows and of the points the tables were built over), a section
+ * table, then every table (basis in float64 and float32, eigenvalues, node
+ * table, edge table, codes and scales, pivot operands, build samples and
+ * cosines, packed gate weights) at 256-byte aligned offsets, and last the
+ * finger_checksum64 of all preceding bytes.  Upper layers attached with
+ * finger_hierarchy_attach are not part of the image (attach them again).
+ *   buf   host, or NULL to query the size into *bytes.
+ *   bytes in: capacity of buf; out: the image size.
+ * Synchronous.  Errors: EINVAL, EOVERFLOW (buffer too small), EDEVICE.
+ */
+FINGER_API int finger_tables_export(const finger_tables* t, void* buf /* host */,
+                                    size_t* bytes /* host */);
+
+/*
+ * finger_tables_import - a handle from an image written by
+ * finger_tables_export, over the caller's data and graph (borrowed as in
+ * finger_build_tables).  The image is checked on the host first (magic,
+ * version, checksum, header ranges, section table: ECORRUPT; n, m,
+ * max_degree against the arguments: EINVAL), before any device call; then
+ * the checksums of the graph rows and of the points (after normalization
+ * for FINGER_ANGULAR) must equal the image's (EINVAL otherwise).  Searches
+ * on the imported handle return exactly what they return on the exported
+ * one.  Synchronous.  Errors: EINVAL, ECORRUPT, ENODEV, ENOMEM, EDEVICE.
+ */
+FINGER_API int finger_tables_import(const void* buf /* host */, size_t bytes, const float* data,
+                                    int64_t n, int32_t m, const int32_t* graph, int32_t max_degree,
+                                    finger_tables** out /* host */, void* stream);
+
+/*
+ * finger_checksum64 - the image checksum: the bytes are read as
+ * little-endian 64-bit words w_0, w_1, ... (the last one zero padded); four
+ * lanes start at h_0..h_3 = 0x243F6A8885A308D3, 0x13198A2E03707344,
+ * 0xA4093822299F31D0, 0x082EFA98EC4E6C89 and word i updates lane j = i mod 4
+ * as h_j = rotl64((h_j xor w_i) * 0x9E3779B97F4A7C15, 31); then x = byte
+ * count and for j = 0..3: x = (x xor h_j) * 0xBF58476D1CE4E5B9, x ^= x >> 29;
+ * the result is x xor (x >> 32).  Host only; p may be NULL when bytes = 0.
+ */
+FINGER_API uint64_t finger_checksum64(const void* p /* host */, size_t bytes);
 
 /* Message for the last failed call on this thread ("" if none). */
 FINGER_API const char* finger_last_error(void);

@@ -65,22 +65,30 @@ def forward(w, X, in_dim: int, H: int, keep: bool = False, bf16_operands: bool =
     return y
 
 
-def loss_and_grad(w, X, t, in_dim: int, H: int):
+def loss_and_grad(w, X, t, in_dim: int, H: int, bf16_operands: bool = False):
     """Mean squared error over the batch and its gradient, by the chain rule
-    written out layer by layer."""
+    written out layer by layer.
+
+    With ``bf16_operands`` every factor of every product is a bfloat16 value
+    (the precision the library's matrix-core kernels compute in): the
+    forward pass as in ``forward``, and in the backward pass the weights and
+    the back-propagated errors dz2, dz1 are rounded before they multiply;
+    dL/dy itself, the bias gradients (plain sums) and all accumulation stay
+    float64."""
     W1, b1, W2, b2, W3, b3 = unpack(w, in_dim, H)
-    y, (X, z1, h1, z2, h2) = forward(w, X, in_dim, H, keep=True)
+    y, (X, z1, h1, z2, h2) = forward(w, X, in_dim, H, keep=True, bf16_operands=bf16_operands)
+    r = round_bf16 if bf16_operands else (lambda a: a)
     B = X.shape[0]
     e = y - np.asarray(t, dtype=np.float64)
     loss = float((e * e).mean())
     dy = 2.0 * e / B                     # dL/dy
     gW3 = h2.T @ dy
     gb3 = dy.sum()
-    dz2 = np.outer(dy, W3) * (z2 > 0)    # dL/dz2
-    gW2 = dz2.T @ h1
+    dz2 = np.outer(dy, r(W3)) * (z2 > 0)  # dL/dz2
+    gW2 = r(dz2).T @ h1
     gb2 = dz2.sum(0)
-    dz1 = (dz2 @ W2) * (z1 > 0)          # dL/dz1
-    gW1 = dz1.T @ X
+    dz1 = (r(dz2) @ r(W2)) * (z1 > 0)    # dL/dz1
+    gW1 = r(dz1).T @ r(X)
     gb1 = dz1.sum(0)
     g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3, [gb3]])
     return loss, g

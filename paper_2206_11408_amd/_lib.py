@@ -15,8 +15,9 @@ FINGER_EDEVICE = -3
 FINGER_ENODEV = -4
 FINGER_EOVERFLOW = -5
 FINGER_EINTERNAL = -6
+FINGER_ECORRUPT = -7
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENODEV",
-                -5: "EOVERFLOW", -6: "EINTERNAL"}
+                -5: "EOVERFLOW", -6: "EINTERNAL", -7: "ECORRUPT"}
 
 L2, ANGULAR, IP = 0, 1, 2
 ENTRY_PIVOT, ENTRY_DESCENT = -1, -2
@@ -37,6 +38,8 @@ EXPORTED = (
     "finger_gate_param_count", "finger_mlp_forward", "finger_mlp_backward",
     "finger_adam_step", "finger_gate_targets", "finger_last_error",
     "finger_hierarchy_attach", "finger_descend", "finger_build_graph",
+    "finger_mlp_backward_workspace_size", "finger_gate_calibrate", "finger_tables_export",
+    "finger_tables_import", "finger_checksum64",
 )
 
 
@@ -55,7 +58,8 @@ class SearchParams(C.Structure):
         ("warmup", C.c_int32), ("k_max", C.c_int32),
         ("k_per_query", C.c_void_p), ("ef_per_query", C.c_void_p),
         ("ef_max", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
-        ("visited_capacity", C.c_int32), ("code_prefetch", C.c_int32),
+        ("visited_capacity", C.c_int32), ("spill_capacity", C.c_int32),
+        ("code_prefetch", C.c_int32), ("screen_layout", C.c_int32),
         ("log_features", C.c_void_p), ("log_targets", C.c_void_p),
         ("log_capacity", C.c_int64), ("log_count", C.c_void_p),
         ("kernel_events", C.c_void_p * 2),
@@ -133,7 +137,17 @@ def load() -> C.CDLL:
     lib.finger_mlp_forward.restype = C.c_int
     lib.finger_mlp_forward.argtypes = [vp, i32, i32, vp, i64, vp, vp]
     lib.finger_mlp_backward.restype = C.c_int
-    lib.finger_mlp_backward.argtypes = [vp, i32, i32, vp, vp, i64, vp, vp, vp]
+    lib.finger_mlp_backward.argtypes = [vp, i32, i32, vp, vp, i64, vp, vp, vp, sz, vp]
+    lib.finger_mlp_backward_workspace_size.restype = C.c_int
+    lib.finger_mlp_backward_workspace_size.argtypes = [i32, i32, i64, P(sz)]
+    lib.finger_gate_calibrate.restype = C.c_int
+    lib.finger_gate_calibrate.argtypes = [vp, i32, i32, vp, vp, i64, P(C.c_double), vp]
+    lib.finger_tables_export.restype = C.c_int
+    lib.finger_tables_export.argtypes = [vp, vp, P(sz)]
+    lib.finger_tables_import.restype = C.c_int
+    lib.finger_tables_import.argtypes = [vp, sz, vp, i64, i32, vp, i32, P(vp), vp]
+    lib.finger_checksum64.restype = C.c_uint64
+    lib.finger_checksum64.argtypes = [vp, sz]
     lib.finger_adam_step.restype = C.c_int
     lib.finger_adam_step.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
                                      C.c_float, i32, vp]

@@ -143,7 +143,7 @@ def finger_build_tables(data: torch.Tensor, graph: torch.Tensor, rank: int = 0,
 def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
                   k_per_query=None, ef_per_query=None, ef_max=0, persistent=0,
                   waves_per_cu=0, visited_capacity=0, code_prefetch=0,
-                  log=None) -> L.SearchParams:
+                  log=None, spill_capacity=0, screen_layout=0) -> L.SearchParams:
     p = L.SearchParams()
     L.load().finger_search_params_init(C.byref(p))
     p.mode, p.k, p.ef, p.entry, p.warmup = mode, k, ef, entry, warmup
@@ -152,6 +152,8 @@ def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
     p.ef_per_query = _ptr(ef_per_query)
     p.ef_max, p.persistent = ef_max, persistent
     p.waves_per_cu, p.visited_capacity = waves_per_cu, visited_capacity
+    p.spill_capacity = spill_capacity
+    p.screen_layout = screen_layout
     p.code_prefetch = code_prefetch
     if log is not None:
         feats, targs, count = log
@@ -169,11 +171,24 @@ def finger_search_workspace_size(tables: Tables, nq: int, p: L.SearchParams) -> 
     return nbytes.value
 
 
+def check_status(ctr: torch.Tensor) -> None:
+    """Raise FingerError(EOVERFLOW) if any query's status counter reports a
+    visited-set overflow (its results are not valid).  Synchronizes."""
+    bad = int(((ctr[:, L.NCOUNTERS - 1] & 1) != 0).sum().item())
+    if bad:
+        raise L.FingerError(L.FINGER_EOVERFLOW,
+                            f"visited set overflowed on {bad} queries; raise visited_capacity "
+                            f"or spill_capacity")
+
+
 def finger_search(tables: Tables, queries: torch.Tensor, p: L.SearchParams | None = None,
-                  out=None, counters: bool = True, **kw):
+                  out=None, counters: bool = True, check: bool = True, **kw):
     """Run finger_search; returns (ids int32 [nq, k_max], dist f32 [nq, k_max],
-    counters int32 [nq, 6] or None).  Pass ``out=(ids, dist, ctr)`` to reuse
-    buffers (timing loops)."""
+    counters int32 [nq, 7] or None).  Pass ``out=(ids, dist, ctr)`` to reuse
+    buffers (timing loops).  With counters and ``check`` the call waits for
+    the search and raises FingerError(EOVERFLOW) if a query's visited set
+    overflowed; ``check=False`` keeps it asynchronous (then call
+    ``check_status`` on the counters)."""
     lib = L.load()
     if p is None:
         p = search_params(**kw)
@@ -191,6 +206,8 @@ def finger_search(tables: Tables, queries: torch.Tensor, p: L.SearchParams | Non
     L.check(lib.finger_search(tables.handle, queries.data_ptr(), nq, C.byref(p), ids.data_ptr(),
                               dist.data_ptr(), _ptr(ctr), tables._ws.data_ptr(),
                               tables._ws.numel(), _stream()))
+    if check and ctr is not None:
+        check_status(ctr)
     return ids, dist, ctr
 
 
@@ -283,17 +300,38 @@ def finger_mlp_forward(weights: torch.Tensor, in_dim: int, hidden: int, x: torch
     return y
 
 
+def finger_mlp_backward_workspace_size(in_dim: int, hidden: int, batch: int) -> int:
+    nbytes = C.c_size_t(0)
+    L.check(L.load().finger_mlp_backward_workspace_size(in_dim, hidden, batch, C.byref(nbytes)))
+    return nbytes.value
+
+
 def finger_mlp_backward(weights: torch.Tensor, in_dim: int, hidden: int, x: torch.Tensor,
                         target: torch.Tensor, grad: torch.Tensor | None = None,
-                        loss: torch.Tensor | None = None):
+                        loss: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Gradient of the mean squared error (finger_mlp_backward).  Pass a
+    ``workspace`` of finger_mlp_backward_workspace_size bytes to reuse it."""
     if grad is None:
         grad = torch.empty_like(weights)
     if loss is None:
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    need = finger_mlp_backward_workspace_size(in_dim, hidden, x.shape[0])
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, x.device)
     L.check(L.load().finger_mlp_backward(weights.data_ptr(), in_dim, hidden, x.data_ptr(),
                                          target.data_ptr(), x.shape[0], grad.data_ptr(),
-                                         loss.data_ptr(), _stream()))
+                                         loss.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                         _stream()))
     return grad, loss
+
+
+def finger_gate_calibrate(weights: torch.Tensor, in_dim: int, hidden: int, x: torch.Tensor,
+                          target: torch.Tensor) -> float:
+    """eps_gate = mean |target - f(x)| over the rows (finger_gate_calibrate)."""
+    out = C.c_double(0.0)
+    L.check(L.load().finger_gate_calibrate(weights.data_ptr(), in_dim, hidden, x.data_ptr(),
+                                           target.data_ptr(), x.shape[0], C.byref(out), _stream()))
+    return out.value
 
 
 def finger_gate_targets(log_features: torch.Tensor, log_targets: torch.Tensor, rows: int,
@@ -308,3 +346,40 @@ def finger_adam_step(weights, grad, m1, m2, lr=1e-3, beta1=0.9, beta2=0.999, eps
     L.check(L.load().finger_adam_step(weights.data_ptr(), grad.data_ptr(), m1.data_ptr(),
                                       m2.data_ptr(), weights.numel(), lr, beta1, beta2, eps,
                                       step, _stream()))
+
+
+# ----------------------------------------------------------- checkpoint
+
+def finger_tables_export(tables: Tables) -> np.ndarray:
+    """The handle's tables image (finger_tables_export) as a uint8 array."""
+    lib = L.load()
+    nbytes = C.c_size_t(0)
+    L.check(lib.finger_tables_export(tables.handle, None, C.byref(nbytes)))
+    buf = np.empty(nbytes.value, dtype=np.uint8)
+    L.check(lib.finger_tables_export(tables.handle, buf.ctypes.data, C.byref(nbytes)))
+    return buf
+
+
+def finger_tables_import(image, data: torch.Tensor, graph: torch.Tensor) -> Tables:
+    """A handle from an image (finger_tables_import) over ``data`` and
+    ``graph``, which must be the points and graph the tables were built on."""
+    buf = np.ascontiguousarray(np.frombuffer(image, dtype=np.uint8) if not isinstance(image, np.ndarray)
+                               else image.view(np.uint8).ravel())
+    data = _dev_f32(data)
+    graph = _dev_i32(graph)
+    h = C.c_void_p()
+    L.check(L.load().finger_tables_import(buf.ctypes.data, buf.size, data.data_ptr(), data.shape[0],
+                                          data.shape[1], graph.data_ptr(), graph.shape[1],
+                                          C.byref(h), _stream()))
+    return Tables(h.value, data, graph)
+
+
+def finger_tables_save(tables: Tables, path: str) -> int:
+    """Write the tables image to ``path``; returns its size in bytes."""
+    buf = finger_tables_export(tables)
+    buf.tofile(path)
+    return int(buf.size)
+
+
+def finger_tables_load(path: str, data: torch.Tensor, graph: torch.Tensor) -> Tables:
+    return finger_tables_import(np.fromfile(path, dtype=np.uint8), data, graph)

@@ -23,7 +23,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-fvisibility=hidden",
 ]
-SOURCES = ["api.hip", "search.hip", "gemm.hip", "build.hip", "gate.hip", "hierarchy.hip", "graph.hip", "eigh.cpp"]
+SOURCES = ["api.hip", "search.hip", "gemm.hip", "build.hip", "gate.hip", "hierarchy.hip", "graph.hip",
+           "tables_io.hip", "eigh.cpp"]
 
 
 def _compile(src: str) -> str:

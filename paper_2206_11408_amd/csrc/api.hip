@@ -16,119 +16,12 @@
 
 #include "../../include/finger.h"
 #include "internal.h"
+#include "abi_util.h"
 
 using finger::Tables;
 using finger::rpad_of;
 
-namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return code;
-}
-
-int ok() {
-  g_err.clear();
-  return FINGER_OK;
-}
-
-#define HIPCHK(x)                                                                          \
-  do {                                                                                     \
-    hipError_t e_ = (x);                                                                   \
-    if (e_ != hipSuccess) return fail(FINGER_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
-  } while (0)
-
-// Allocation with an injectable failure (FINGER_FAULT_INJECT=alloc makes
-// every allocation fail, to test the error path).
-int dev_alloc(void** p, size_t bytes, const char* what) {
-  *p = nullptr;
-  if (bytes == 0) return FINGER_OK;
-  const char* fi = std::getenv("FINGER_FAULT_INJECT");
-  if (fi != nullptr && std::strcmp(fi, "alloc") == 0)
-    return fail(FINGER_ENOMEM, "allocation of %zu bytes for %s failed (injected)", bytes, what);
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(FINGER_ENOMEM, "allocation of %zu bytes for %s failed: %s", bytes, what,
-                hipGetErrorString(e));
-  }
-  return FINGER_OK;
-}
-
-int check_device(int* dev_out) {
-  int count = 0;
-  hipError_t e = hipGetDeviceCount(&count);
-  if (e != hipSuccess || count <= 0) {
-    (void)hipGetLastError();
-    return fail(FINGER_ENODEV, "no HIP device available");
-  }
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  hipDeviceProp_t prop;
-  HIPCHK(hipGetDeviceProperties(&prop, dev));
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(FINGER_ENODEV, "device %d is %s; this library is built for gfx950", dev,
-                prop.gcnArchName);
-  if (dev_out) *dev_out = dev;
-  return FINGER_OK;
-}
-
-int cu_count() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-    return 256;
-  return cus;
-}
-
-size_t align256(size_t x) { return (x + 255) / 256 * 256; }
-
-int next_pow2(int x) {
-  int p = 1;
-  while (p < x) p <<= 1;
-  return p;
-}
-
-void free_tables(Tables* t) {
-  if (t == nullptr) return;
-  void* dev_ptrs[] = {t->data_owned, t->P, t->cc, t->pc, t->alpha, t->rho, t->codes, t->scale,
-                      t->piv_ids, t->qprep_B, t->qprep_Bnorm, t->piv_b16, t->piv_norm, t->samples, t->xy, t->gate_w,
-                      t->gate_b, t->h_row0, t->h_upper};
-  for (void* p : dev_ptrs)
-    if (p) (void)hipFree(p);
-  std::free(t->P64_host);
-  std::free(t->eig_host);
-  delete t;
-}
-
-struct Guard {  // frees a half-built handle on error paths
-  Tables* t;
-  ~Guard() { free_tables(t); }
-};
-
-template <typename T>
-struct DevBuf {  // scoped temporary device buffer
-  T* p = nullptr;
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  void reset() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-  }
-  ~DevBuf() { reset(); }
-};
-
-}  // namespace
+using namespace finger::abi;
 
 extern "C" {
 
@@ -207,6 +100,7 @@ int finger_build_tables(const float* data, int64_t n, int32_t m, const int32_t* 
   t->code_type = p->code_type;
   t->metric = p->metric;
   t->sigma_mode = p->sigma_mode;
+  t->seed = p->seed;
   t->graph = graph;
   const int rpad = rpad_of(t->r);
 
@@ -498,6 +392,8 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   if (vis_cap == 0) vis_cap = std::min(8192, std::max(1024, next_pow2(24 * ef_max)));
   if (p->code_prefetch < -1 || p->code_prefetch > 1)
     return fail(FINGER_EINVAL, "code_prefetch = %d must be -1, 0 or 1", p->code_prefetch);
+  if (p->screen_layout < 0 || p->screen_layout > 2)
+    return fail(FINGER_EINVAL, "screen_layout = %d must be 0, 1 or 2", p->screen_layout);
   if (vis_cap < 256 || (vis_cap & (vis_cap - 1)) != 0)
     return fail(FINGER_EINVAL, "visited_capacity = %d must be a power of two >= 256", vis_cap);
   const int gate_in = p->mode == FINGER_MODE_GATED ? t->gate_in : 0;
@@ -523,7 +419,10 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   pl->off_ent = off; off += align256((size_t)nq * 4);
   pl->off_queue = off; off += 256;
   pl->off_qscr = off; off += align256(query_prep_scratch_bytes(*t, nq));
-  const int spill_slots = std::min(16384, std::max(1024, next_pow2(8 * ef_max)));
+  int spill_slots = p->spill_capacity;
+  if (spill_slots == 0) spill_slots = std::min(65536, std::max(1024, next_pow2(ef_max * t->deg)));
+  if (spill_slots < 64 || spill_slots > (1 << 20) || (spill_slots & (spill_slots - 1)) != 0)
+    return fail(FINGER_EINVAL, "spill_capacity = %d must be a power of two in [64, 2^20]", spill_slots);
   pl->off_spill = off; off += align256((size_t)waves * spill_slots * 4);
   pl->spill_slots = spill_slots;
   // angular metric: the search reads unit-normalized copies of the queries
@@ -615,6 +514,7 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.waves = pl.waves;
   L.persistent = p->persistent;
   L.prefetch = p->code_prefetch > 0 || (p->code_prefetch == 0 && t->code_type != FINGER_CODE_F32);
+  L.coalesced = p->screen_layout != 2;
   L.log_x = p->log_features;
   L.log_y = p->log_targets;
   L.log_cap = p->log_capacity;
@@ -1073,18 +973,55 @@ int finger_gate_targets(const float* log_features, const float* log_targets, int
 int finger_mlp_forward(const float* weights, int32_t in_dim, int32_t hidden, const float* x,
                        int64_t batch, float* y, void* stream) {
   if (!weights || !x || !y) return fail(FINGER_EINVAL, "NULL pointer");
-  if (in_dim < 1 || hidden < 1 || hidden > 64 || batch < 0) return fail(FINGER_EINVAL, "bad sizes");
+  if (in_dim < 1 || in_dim > 512 || hidden < 1 || hidden > 64 || batch < 0)
+    return fail(FINGER_EINVAL, "bad sizes (1 <= in_dim <= 512, 1 <= hidden <= 64, batch >= 0)");
   HIPCHK(finger::launch_mlp_forward(weights, in_dim, hidden, x, batch, y, static_cast<hipStream_t>(stream)));
   return ok();
 }
 
+int finger_mlp_backward_workspace_size(int32_t in_dim, int32_t hidden, int64_t batch, size_t* bytes) {
+  if (bytes == nullptr) return fail(FINGER_EINVAL, "NULL pointer");
+  if (in_dim < 1 || in_dim > 512 || hidden < 1 || hidden > 64 || batch < 1)
+    return fail(FINGER_EINVAL, "bad sizes (1 <= in_dim <= 512, 1 <= hidden <= 64, batch >= 1)");
+  *bytes = finger::mlp_backward_scratch_bytes(in_dim, hidden, batch);
+  return ok();
+}
+
 int finger_mlp_backward(const float* weights, int32_t in_dim, int32_t hidden, const float* x,
-                        const float* target, int64_t batch, float* grad, float* loss, void* stream) {
+                        const float* target, int64_t batch, float* grad, float* loss,
+                        void* workspace, size_t workspace_bytes, void* stream) {
   if (!weights || !x || !target || !grad) return fail(FINGER_EINVAL, "NULL pointer");
-  if (in_dim < 1 || in_dim > 260 || hidden < 1 || hidden > 64 || batch < 1)
-    return fail(FINGER_EINVAL, "bad sizes (in_dim <= 260, hidden <= 64, batch >= 1)");
-  HIPCHK(finger::launch_mlp_backward(weights, in_dim, hidden, x, target, batch, grad, loss,
+  if (in_dim < 1 || in_dim > 512 || hidden < 1 || hidden > 64 || batch < 1)
+    return fail(FINGER_EINVAL, "bad sizes (1 <= in_dim <= 512, 1 <= hidden <= 64, batch >= 1)");
+  const size_t need = finger::mlp_backward_scratch_bytes(in_dim, hidden, batch);
+  if (workspace == nullptr || workspace_bytes < need)
+    return fail(FINGER_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(FINGER_EINVAL, "workspace must be 256-byte aligned");
+  HIPCHK(finger::launch_mlp_backward(weights, in_dim, hidden, x, target, batch, grad, loss, workspace,
                                      static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+int finger_gate_calibrate(const float* weights, int32_t in_dim, int32_t hidden, const float* x,
+                          const float* target, int64_t rows, double* eps_gate, void* stream) {
+  if (!weights || !x || !target || !eps_gate) return fail(FINGER_EINVAL, "NULL pointer");
+  if (in_dim < 1 || in_dim > 512 || hidden < 1 || hidden > 64 || rows < 1)
+    return fail(FINGER_EINVAL, "bad sizes (1 <= in_dim <= 512, 1 <= hidden <= 64, rows >= 1)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf<float> y;
+  int st = dev_alloc(reinterpret_cast<void**>(&y.p), (size_t)rows * 4, "gate outputs");
+  if (st != FINGER_OK) return st;
+  const int nb = finger::abs_err_blocks(rows);
+  DevBuf<double> parts;
+  if ((st = dev_alloc(reinterpret_cast<void**>(&parts.p), (size_t)nb * 8, "error sums")) != FINGER_OK) return st;
+  HIPCHK(finger::launch_mlp_forward(weights, in_dim, hidden, x, rows, y.p, s));
+  HIPCHK(finger::launch_abs_err_parts(y.p, target, rows, parts.p, s));
+  std::vector<double> hp((size_t)nb);
+  HIPCHK(hipMemcpyAsync(hp.data(), parts.p, (size_t)nb * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double sum = 0.0;
+  for (double v : hp) sum += v;
+  *eps_gate = sum / (double)rows;
   return ok();
 }
 

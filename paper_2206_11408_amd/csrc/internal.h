@@ -47,6 +47,7 @@ struct Tables {
   int device = 0;
   int64_t n = 0;
   int32_t m = 0, r = 0, deg = 0, code_type = 0, metric = 0, sigma_mode = 0;
+  uint64_t seed = 0;               // build seed of the samples
   const float* data = nullptr;     // points the search reads (borrowed, or data_owned)
   float* data_owned = nullptr;     // normalized copy for FINGER_ANGULAR
   const int32_t* graph = nullptr;  // borrowed
@@ -167,6 +168,7 @@ struct SearchLaunch {
   int waves;        // grid size in waves
   int persistent;
   int prefetch;     // issue every slot's edge code with the adjacency row
+  int coalesced;    // FINGER mode: coalesced screen (code rows of 32..256 bytes, degree <= 32)
   float* log_x;
   float* log_y;
   int64_t log_cap;
@@ -211,8 +213,13 @@ hipError_t launch_exact_knn(const float* data, int64_t n, int m, const float* Q,
 // gate
 hipError_t launch_mlp_forward(const float* w, int in, int H, const float* x, int64_t B, float* y,
                               hipStream_t s);
+size_t mlp_backward_scratch_bytes(int in, int H, int64_t B);
 hipError_t launch_mlp_backward(const float* w, int in, int H, const float* x, const float* tgt,
-                               int64_t B, float* grad, float* loss, hipStream_t s);
+                               int64_t B, float* grad, float* loss, void* scratch, hipStream_t s);
+// per-block float64 sums of |t - y| (abs_err_blocks(rows) of them)
+int abs_err_blocks(int64_t rows);
+hipError_t launch_abs_err_parts(const float* y, const float* t, int64_t rows, double* parts,
+                                hipStream_t s);
 hipError_t launch_adam(float* w, const float* g, float* m1, float* m2, int64_t cnt, float lr,
                        float b1, float b2, float eps, int step, hipStream_t s);
 hipError_t launch_gate_targets(const float* x, const float* y, int64_t rows, int r, float* out,

@@ -6,8 +6,9 @@
 3. ``train``: minibatch Adam on the mean squared error, forward/backward and
    the update all in the library's kernels (bf16 operands, float32
    accumulation); torch only holds buffers and draws the batch order.
-4. ``calibrate``: eps_gate = mean |t - f(x)| on held-out rows (the analogue
-   of Algorithm 2's correction term), then ``finger_gate_attach``.
+4. ``calibrate``: eps_gate = mean |t - f(x)| on held-out rows, the analogue
+   of Algorithm 2's correction term, computed by the library
+   (``finger_gate_calibrate``), then ``finger_gate_attach``.
 """
 from __future__ import annotations
 
@@ -55,6 +56,8 @@ def train(X: torch.Tensor, t: torch.Tensor, hidden: int = 64, epochs: int = 2, b
     m1 = torch.zeros_like(w)
     m2 = torch.zeros_like(w)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ws = torch.empty(max(256, api.finger_mlp_backward_workspace_size(in_dim, hidden, batch)),
+                     dtype=torch.uint8, device=dev)
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
     n = X.shape[0]
@@ -67,7 +70,7 @@ def train(X: torch.Tensor, t: torch.Tensor, hidden: int = 64, epochs: int = 2, b
             idx = order[s:s + batch]
             xb = X.index_select(0, idx).contiguous()
             tb = t.index_select(0, idx).contiguous()
-            api.finger_mlp_backward(w, in_dim, hidden, xb, tb, g, loss)
+            api.finger_mlp_backward(w, in_dim, hidden, xb, tb, g, loss, workspace=ws)
             step += 1
             api.finger_adam_step(w, g, m1, m2, lr=lr, step=step)
             if (step % 64) == 0:
@@ -79,11 +82,9 @@ def train(X: torch.Tensor, t: torch.Tensor, hidden: int = 64, epochs: int = 2, b
 
 
 def calibrate(weights: np.ndarray, X: torch.Tensor, t: torch.Tensor, hidden: int) -> float:
-    """eps_gate = mean |t - f(x)| over the given rows (float64 on the host)."""
+    """eps_gate = mean |t - f(x)| over the given rows (finger_gate_calibrate)."""
     w = torch.as_tensor(weights, dtype=torch.float32, device=X.device)
-    y = api.finger_mlp_forward(w, X.shape[1], hidden, X.contiguous())
-    err = np.abs(t.double().cpu().numpy() - y.double().cpu().numpy())
-    return float(err.mean())
+    return api.finger_gate_calibrate(w, X.shape[1], hidden, X.contiguous(), t.contiguous())
 
 
 def fit_gate(tables: api.Tables, train_queries: torch.Tensor, ef: int, hidden: int = 64,

@@ -184,3 +184,82 @@ def test_gate_param_count():
     # in = 2r + 4 with r = 64, H = 64: 64*132 + 64 + 64*64 + 64 + 64 + 1
     assert lib.finger_gate_param_count(132, 64) == 12737
     assert lib.finger_gate_param_count(0, 64) == 0
+
+
+# ----------------------------------------------------------- checkpoint
+
+_M = (1 << 64) - 1
+
+
+def _checksum_spec(data: bytes) -> int:
+    """finger_checksum64 written out from its definition in finger.h."""
+    h = [0x243F6A8885A308D3, 0x13198A2E03707344, 0xA4093822299F31D0, 0x082EFA98EC4E6C89]
+    pad = data + b"\0" * (-len(data) % 8)
+    for i in range(len(pad) // 8):
+        w = int.from_bytes(pad[8 * i:8 * i + 8], "little")
+        x = ((h[i % 4] ^ w) * 0x9E3779B97F4A7C15) & _M
+        h[i % 4] = ((x << 31) | (x >> 33)) & _M
+    x = len(data)
+    for j in range(4):
+        x = ((x ^ h[j]) * 0xBF58476D1CE4E5B9) & _M
+        x ^= x >> 29
+    return x ^ (x >> 32)
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 8, 9, 31, 32, 33, 200])
+def test_checksum_matches_its_definition(n):
+    lib = L.load()
+    data = bytes((37 * i + 11) & 0xFF for i in range(n))
+    buf = C.create_string_buffer(data, max(n, 1))
+    assert lib.finger_checksum64(buf if n else None, n) == _checksum_spec(data)
+
+
+def _image(n=10, m=32, deg=8, version=1, magic=b"FINGERTB", extra=b""):
+    import struct
+    hdr = bytearray(200)
+    hdr[0:8] = magic
+    struct.pack_into("<IIq", hdr, 8, version, 0, n)
+    struct.pack_into("<iii", hdr, 24, m, 0, deg)
+    body = bytes(hdr) + extra
+    return body + _checksum_spec(body).to_bytes(8, "little")
+
+
+def test_import_checks_the_image_on_the_host():
+    """Damaged images are refused before any device call (this runs without
+    a GPU); an intact one gets past the host checks."""
+    import torch
+    lib = L.load()
+    h = C.c_void_p()
+
+    def imp(img, n=10, m=32, deg=8):
+        b = C.create_string_buffer(img, len(img))
+        return lib.finger_tables_import(b, len(img), 1 << 20, n, m, 1 << 20, deg, C.byref(h), None)
+
+    good = _image()
+    flipped = bytearray(good)
+    flipped[40] ^= 1
+    assert imp(bytes(flipped)) == L.FINGER_ECORRUPT
+    assert "checksum" in lib.finger_last_error().decode()
+    assert imp(good[:100]) == L.FINGER_ECORRUPT
+    assert imp(_image(magic=b"NOTFINGR")) == L.FINGER_ECORRUPT
+    assert imp(_image(version=2)) == L.FINGER_ECORRUPT
+    assert imp(good, n=11) == L.FINGER_EINVAL
+    assert imp(good, m=36) == L.FINGER_EINVAL
+    st = imp(good)
+    if not torch.cuda.is_available():
+        assert st == L.FINGER_ENODEV, lib.finger_last_error().decode()
+    assert lib.finger_tables_export(None, None, C.byref(C.c_size_t(0))) == L.FINGER_EINVAL
+
+
+def test_mlp_backward_needs_a_workspace():
+    lib = L.load()
+    nb = C.c_size_t(0)
+    assert lib.finger_mlp_backward_workspace_size(132, 64, 4096, C.byref(nb)) == L.FINGER_OK
+    # 128 tiles of 32 samples, each a partial gradient plus its loss term
+    assert nb.value == (128 * 12737 + 128) * 4
+    assert lib.finger_mlp_backward_workspace_size(600, 64, 10, C.byref(nb)) == L.FINGER_EINVAL
+    st = lib.finger_mlp_backward(1 << 20, 132, 64, 1 << 20, 1 << 20, 4096, 1 << 20, None, 1 << 20,
+                                 16, None)
+    assert st == L.FINGER_EINVAL and "workspace" in lib.finger_last_error().decode()
+    st = lib.finger_mlp_backward(1 << 20, 132, 64, 1 << 20, 1 << 20, 4096, 1 << 20, None, None, 0, None)
+    assert st == L.FINGER_EINVAL

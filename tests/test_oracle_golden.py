@@ -132,11 +132,12 @@ def test_gate_forward_hand_values(gate, bf16):
         assert z2[0].tolist() == row["z2"] and h2[0].tolist() == row["h2"]
 
 
-def test_gate_backward_hand_values(gate):
+@pytest.mark.parametrize("bf16", [False, True])
+def test_gate_backward_hand_values(gate, bf16):
     w = _gate_params(gate)
     b = gate["backward"]
     loss, g = loss_and_grad(w, np.array(b["x"], dtype=np.float64), np.array(b["target"]),
-                            gate["in_dim"], gate["hidden"])
+                            gate["in_dim"], gate["hidden"], bf16_operands=bf16)
     assert loss == b["loss"]
     gg = b["grad"]
     want = np.concatenate([np.ravel(gg["W1"]), gg["b1"], np.ravel(gg["W2"]), gg["b2"], gg["W3"],
