@@ -85,6 +85,7 @@ struct KArgs {
   int spill_slots;
   int vis_cap;
   int waves_per_block;
+  int coalesced;  // FINGER mode: use the coalesced screen where it applies
   int lds_wave_bytes;
   int lds_shared_bytes;
   // gate (weights transposed: W1T [in][H], W2T [H][H], W3 [H]; biases float)
@@ -237,6 +238,75 @@ __device__ __forceinline__ float group_sum_rt(float v, int g) {
   if (g >= 32) v += shfl_xor_f(v, 16);
   if (g >= 64) v += shfl_xor_f(v, 32);
   return v;
+}
+
+// ------------------------------------------------ coalesced screening
+// FINGER mode with code rows of at most 256 bytes and at most 32 slots per
+// node: a node's codes are one contiguous block of deg x CB bytes, and load
+// instruction i of a screen covers its bytes [1024 i, 1024 i + 1024): lane
+// l holds the 16 bytes at 1024 i + 16 l, i.e. piece p = l % LC of slot
+// i SPI + l / LC (LC = CB / 16 lanes per code, SPI = 64 / LC codes per
+// instruction).  Every lane multiplies its pieces with the same FE-element
+// fragment of w (held in registers) and the LC / 2 partial dot products of
+// a group of LC lanes are summed by a transposed butterfly of DPP moves
+// inside the group, after which lane p of the group holds the full dot
+// product of instruction p / 2, i.e. of slot (p / 2) SPI + l / LC.
+template <int CODE>
+constexpr int code_esz() { return CODE == FINGER_CODE_F32 ? 4 : (CODE == FINGER_CODE_BF16 ? 2 : 1); }
+
+// partial dot product of one 16-byte piece with the lane's w fragment
+template <int CODE>
+__device__ __forceinline__ float piece_dot(const uint4& v, const float* __restrict__ w);
+template <>
+__device__ __forceinline__ float piece_dot<FINGER_CODE_F32>(const uint4& v, const float* __restrict__ w) {
+  return w[0] * __uint_as_float(v.x) + w[1] * __uint_as_float(v.y) + w[2] * __uint_as_float(v.z) +
+         w[3] * __uint_as_float(v.w);
+}
+template <>
+__device__ __forceinline__ float piece_dot<FINGER_CODE_BF16>(const uint4& v, const float* __restrict__ w) {
+  const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    s += w[2 * j] * __uint_as_float(x[j] << 16) + w[2 * j + 1] * __uint_as_float(x[j] & 0xffff0000u);
+  return s;
+}
+template <>
+__device__ __forceinline__ float piece_dot<FINGER_CODE_FP8E4M3>(const uint4& v, const float* __restrict__ w) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const uint32_t x[4] = {v.x, v.y, v.z, v.w};
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)x[j], false);
+    const f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)x[j], true);
+    s += w[4 * j] * lo.x + w[4 * j + 1] * lo.y + w[4 * j + 2] * hi.x + w[4 * j + 3] * hi.y;
+  }
+  return s;
+}
+
+// one butterfly step: K values -> K / 2; the lane whose partner (under the
+// DPP pairing CTRL) sits below it keeps the upper half
+template <int K, int CTRL>
+__device__ __forceinline__ void bfly_split(float* v, bool upper) {
+#pragma unroll
+  for (int j = 0; j < K / 2; ++j) {
+    const float keep = upper ? v[j + K / 2] : v[j];
+    const float send = upper ? v[j] : v[j + K / 2];
+    v[j] = keep + dpp_f<CTRL>(send);
+  }
+}
+
+// v[0..LC/2): this lane's partials of instructions 0..LC/2-1; returns the
+// group's sum for instruction p / 2 (p = lane within the group).  Pairings:
+// row_mirror (i <-> 15 - i) splits on bit 3, row_half_mirror (i <-> 7 - i)
+// on bit 2, quad swaps on bits 1 and 0.
+template <int LC>
+__device__ __forceinline__ float bfly_reduce(float* v, int p) {
+  if constexpr (LC >= 16) bfly_split<8, kDppMirror>(v, (p & 8) != 0);
+  if constexpr (LC >= 8) bfly_split<4, kDppHalfMirror>(v, (p & 4) != 0);
+  if constexpr (LC >= 4) bfly_split<2, kDppXor2>(v, (p & 2) != 0);
+  return v[0] + dpp_f<kDppXor1>(v[0]);
 }
 
 template <int G, int T4>
@@ -394,8 +464,17 @@ __device__ __forceinline__ void gate_tiles(const GateLayout& GL, const uint16_t*
   }
 }
 
-template <int MODE, int CODE, int G, int T4, bool PREFETCH>
+template <int MODE, int CODE, int G, int T4, bool PREFETCH, int LC>
 __device__ __forceinline__ void search_body(const KArgs& a) {
+  // LC > 0: the coalesced screen (FINGER mode only); the query then stays in
+  // registers when a lane needs at most four float4 of it and holds at most
+  // four code pieces
+  static_assert(LC == 0 || MODE == FINGER_MODE_FINGER, "coalesced screen is for FINGER mode");
+  constexpr bool kCoal = LC > 0;
+  constexpr bool kQReg = MODE == FINGER_MODE_PLAIN || (kCoal && T4 <= 4 && LC <= 8);
+  constexpr int kFE = 16 / code_esz<CODE>();          // code elements per 16-byte piece
+  constexpr int kSPI = kCoal ? 64 / LC : 1;           // slots per load instruction
+  constexpr int kNI = kCoal ? LC / 2 : 1;             // load instructions for 32 slots
   extern __shared__ __align__(16) char smem[];
   const int l = lane_id();
   // wave-uniform values are kept in scalar registers (readfirstlane), so the
@@ -416,8 +495,8 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   float4* qsh = reinterpret_cast<float4*>(pqv + a.rpad);  // [m] the query (screening modes)
   float* feat = reinterpret_cast<float*>(qsh) + (MODE != FINGER_MODE_PLAIN ? a.m : 0);
   // gated: feat = [spp][r + 4], then [64] hidden
-  // screening modes keep the query in LDS (registers go to the screen)
-  const float4* qlds = (MODE != FINGER_MODE_PLAIN) ? qsh : nullptr;
+  // the other screening modes keep the query in LDS (registers go to the screen)
+  const float4* qlds = kQReg ? nullptr : qsh;
 
   const uint16_t* gw = nullptr;
   const float* gb = nullptr;
@@ -455,6 +534,11 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   // defined values; their dot products are masked out
   Chunk<CODE> code;
   code.zero();
+  // coalesced screen: piece lp of the codes of slots i kSPI + lg, and the
+  // slot whose decision this lane computes
+  const int lp = kCoal ? l % (kCoal ? LC : 1) : 0;
+  const int lg = kCoal ? l / (kCoal ? LC : 1) : 0;
+  const int myslot = (lp >> 1) * kSPI + lg;
 
   for (int64_t it = 0;; ++it) {
     int64_t qi;
@@ -476,8 +560,8 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       status |= 2;
     }
 
-    float4 qv[MODE == FINGER_MODE_PLAIN ? T4 : 1];
-    if constexpr (MODE == FINGER_MODE_PLAIN) {
+    float4 qv[kQReg ? T4 : 1];
+    if constexpr (kQReg) {
       load_query<G, T4>(a, qi, qv);
     } else {
       const float4* q4 = reinterpret_cast<const float4*>(a.queries + qi * a.m);
@@ -540,7 +624,40 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       // this round trip so that forming w below waits on no memory access
       // (a wait there would also drain the code loads issued before it)
       float pcv[4] = {0.f, 0.f, 0.f, 0.f};
-      if constexpr (MODE != FINGER_MODE_PLAIN) {
+      // coalesced screen: this lane's piece of P c, the fp8 scale, and the
+      // code pieces (zero where not loaded, so that nothing carries over
+      // from one expansion to the next)
+      float pcf[kCoal ? kFE : 1];
+      float sclv = 1.f;
+      uint4 craw[kNI];
+#pragma unroll
+      for (int i = 0; i < kNI; ++i) craw[i] = make_uint4(0u, 0u, 0u, 0u);
+      if constexpr (kCoal) {
+        if (screening) {
+          if (myslot < a.deg) {
+            al = a.alpha[(int64_t)cur * a.deg + myslot];
+            rh = a.rho[(int64_t)cur * a.deg + myslot];
+          }
+          ccv = a.cc[cur];
+          const float4* pc4 = reinterpret_cast<const float4*>(a.pc + (int64_t)cur * a.rpad + lp * kFE);
+#pragma unroll
+          for (int t = 0; t < kFE / 4; ++t) {
+            const float4 v = pc4[t];
+            pcf[4 * t] = v.x;
+            pcf[4 * t + 1] = v.y;
+            pcf[4 * t + 2] = v.z;
+            pcf[4 * t + 3] = v.w;
+          }
+          if constexpr (CODE == FINGER_CODE_FP8E4M3) sclv = a.scale[cur];
+          if constexpr (PREFETCH) {
+            const uint4* cb = reinterpret_cast<const uint4*>(static_cast<const char*>(a.codes) +
+                                                             (int64_t)cur * a.deg * (LC * 16));
+#pragma unroll
+            for (int i = 0; i < kNI; ++i)
+              if (i * kSPI + lg < a.deg) craw[i] = cb[64 * i + l];
+          }
+        }
+      } else if constexpr (MODE != FINGER_MODE_PLAIN) {
         if (screening) {
           if (csub < a.deg) {
             al = a.alpha[(int64_t)cur * a.deg + csub];
@@ -565,7 +682,61 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       uint64_t survm = newm;
       bool logging = false;
       int64_t log_base = 0;
-      if constexpr (MODE != FINGER_MODE_PLAIN) {
+      if constexpr (kCoal) {
+        if (screening) {
+          // 4. screening, coalesced: codes of the new slots (unless requested
+          // with the adjacency row), one 1 KB span of the block per instruction
+          n_scr += S;
+          ++n_prep;
+          if constexpr (!PREFETCH) {
+            const uint4* cb = reinterpret_cast<const uint4*>(static_cast<const char*>(a.codes) +
+                                                             (int64_t)cur * a.deg * (LC * 16));
+#pragma unroll
+            for (int i = 0; i < kNI; ++i) {
+              const int slot = i * kSPI + lg;
+              if (slot < a.deg && ((newm >> slot) & 1ull)) craw[i] = cb[64 * i + l];
+            }
+          }
+          // query side (Section 3.2 and Supplementary G), as below; w is
+          // formed piecewise: this lane's kFE elements of Pq - alpha_q P c
+          const float qc = a.ip ? -dcur : 0.5f * (qq + ccv - dcur);
+          const float aq = ccv > 0.f ? qc / ccv : 0.f;
+          const float rq2 = fmaxf(qq - aq * qc, 0.f);
+          const float rq = sqrtf(rq2);
+          float wf[kFE];
+          float w2 = 0.f;
+          const float4* pq4 = reinterpret_cast<const float4*>(pqv + lp * kFE);
+#pragma unroll
+          for (int t = 0; t < kFE / 4; ++t) {
+            const float4 q = pq4[t];
+            wf[4 * t] = q.x - aq * pcf[4 * t];
+            wf[4 * t + 1] = q.y - aq * pcf[4 * t + 1];
+            wf[4 * t + 2] = q.z - aq * pcf[4 * t + 2];
+            wf[4 * t + 3] = q.w - aq * pcf[4 * t + 3];
+          }
+#pragma unroll
+          for (int e = 0; e < kFE; ++e) w2 += wf[e] * wf[e];
+          w2 = group_sum<LC>(w2);
+          const float inv_w = w2 > 0.f ? 1.0f / sqrtf(w2) : 0.f;
+          float part[kNI];
+#pragma unroll
+          for (int i = 0; i < kNI; ++i) part[i] = piece_dot<CODE>(craw[i], wf);
+          const float dot = bfly_reduce<LC>(part, lp);
+          // Algorithm 3 and Eq. 2 for slot myslot (lanes with even lp decide)
+          const bool slot_new = myslot < a.deg && ((newm >> myslot) & 1ull);
+          const float t_hat = dot * sclv * inv_w;
+          const float t = (t_hat - a.mu_hat) * a.dm_scale + a.mu + a.eps;
+          const float da = aq - al;
+          const float est = a.ip ? -(aq * al * ccv + rq * rh * t) : da * da * ccv + rq2 + rh * rh - 2.f * rq * rh * t;
+          const int skip_here = (slot_new && est > ub2) ? 1 : 0;
+          // adjacency lane s takes the decision of lane (s % kSPI) LC + 2 (s / kSPI)
+          const int src = l < a.deg ? (l % kSPI) * LC + 2 * (l / kSPI) : 0;
+          const bool skip_l = __shfl(skip_here, src, 64) != 0;
+          const bool keep = isnew && !skip_l;
+          survm = ballot(keep);
+          n_skip += S - popc64(survm);
+        }
+      } else if constexpr (MODE != FINGER_MODE_PLAIN) {
         if (screening) {
           // 4. screening
           n_scr += S;
@@ -827,17 +998,17 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   }
 }
 
-template <int MODE, int CODE, int G, int T4, bool PF>
+template <int MODE, int CODE, int G, int T4, bool PF, int LC>
 __global__ void __launch_bounds__(256) k_search(KArgs a) {
-  search_body<MODE, CODE, G, T4, PF>(a);
+  search_body<MODE, CODE, G, T4, PF, LC>(a);
 }
 
 // FINGER screening: hold the register budget of four waves per SIMD (the
 // search is latency bound, so resident waves matter more than a few spills)
-template <int MODE, int CODE, int G, int T4, bool PF>
+template <int MODE, int CODE, int G, int T4, bool PF, int LC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_search_w4(KArgs a) {
-  search_body<MODE, CODE, G, T4, PF>(a);
+  search_body<MODE, CODE, G, T4, PF, LC>(a);
 }
 
 template <typename F>
@@ -849,23 +1020,43 @@ hipError_t launch_fn(F fn, const KArgs& a, int blocks, int lds, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int MODE, int CODE, int G, int T4, bool PF>
+template <int MODE, int CODE, int G, int T4, bool PF, int LC>
 hipError_t launch_k(const KArgs& a, int blocks, int lds, hipStream_t s) {
   // the register cap applies up to m = 512; beyond, a vector needs 8 float4
   // per lane and the capped build spills heavily (there it also returned
   // run-to-run differing results with BF16 codes requested ahead, so the
   // uncapped build is used)
   if constexpr (MODE == FINGER_MODE_FINGER && G < 64)
-    return launch_fn(k_search_w4<MODE, CODE, G, T4, PF>, a, blocks, lds, s);
+    return launch_fn(k_search_w4<MODE, CODE, G, T4, PF, LC>, a, blocks, lds, s);
   else
-    return launch_fn(k_search<MODE, CODE, G, T4, PF>, a, blocks, lds, s);
+    return launch_fn(k_search<MODE, CODE, G, T4, PF, LC>, a, blocks, lds, s);
+}
+
+template <int MODE, int CODE, bool PF, int LC>
+hipError_t launch_dims_lc(const KArgs& a, int blocks, int lds, hipStream_t s) {
+  if (a.m4 <= 32) return launch_k<MODE, CODE, 8, 4, PF, LC>(a, blocks, lds, s);
+  if (a.m4 <= 128) return launch_k<MODE, CODE, 32, 4, PF, LC>(a, blocks, lds, s);
+  return launch_k<MODE, CODE, 64, 8, PF, LC>(a, blocks, lds, s);
 }
 
 template <int MODE, int CODE, bool PF>
 hipError_t launch_dims(const KArgs& a, int blocks, int lds, hipStream_t s) {
-  if (a.m4 <= 32) return launch_k<MODE, CODE, 8, 4, PF>(a, blocks, lds, s);
-  if (a.m4 <= 128) return launch_k<MODE, CODE, 32, 4, PF>(a, blocks, lds, s);
-  return launch_k<MODE, CODE, 64, 8, PF>(a, blocks, lds, s);
+  if constexpr (MODE == FINGER_MODE_FINGER) {
+    // the coalesced screen where a code row is 32..256 bytes and a node has
+    // at most 32 slots
+    const int cb = a.rpad * code_esz<CODE>();
+    if (a.coalesced && a.deg <= 32) {
+      if (cb == 256) return launch_dims_lc<MODE, CODE, PF, 16>(a, blocks, lds, s);
+      if (cb == 128) return launch_dims_lc<MODE, CODE, PF, 8>(a, blocks, lds, s);
+      if constexpr (CODE != FINGER_CODE_F32) {
+        if (cb == 64) return launch_dims_lc<MODE, CODE, PF, 4>(a, blocks, lds, s);
+      }
+      if constexpr (CODE == FINGER_CODE_FP8E4M3) {
+        if (cb == 32) return launch_dims_lc<MODE, CODE, PF, 2>(a, blocks, lds, s);
+      }
+    }
+  }
+  return launch_dims_lc<MODE, CODE, PF, 0>(a, blocks, lds, s);
 }
 
 template <int MODE, bool PF>
@@ -966,6 +1157,7 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   a.eps_gate = (float)t.eps_gate;
   // one query wave per workgroup keeps LDS allocation fine grained
   a.waves_per_block = 1;
+  a.coalesced = L.coalesced;
   a.lds_shared_bytes = 0;
   a.lds_wave_bytes = wave_bytes(L.ef_max, L.vis_cap, L.mode == FINGER_MODE_PLAIN ? 0 : t.r, t.m,
                                 gated ? a.gate_in : 0);
