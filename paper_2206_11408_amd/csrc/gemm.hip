@@ -122,6 +122,66 @@ __global__ void __launch_bounds__(256) k_qprep(const float* Q, int64_t nq, const
       }
 }
 
+// Pq for long vectors: a workgroup owns 16 queries (many more workgroups
+// than 64-row tiles give, so the latency of each K slab overlaps across
+// them) and walks the columns in groups of 64, wave w taking columns
+// 16 w .. 16 w + 15 of a group.  The next slab's global loads are in flight
+// while the current one is multiplied (LDS double buffer).  The MFMA steps
+// and their operands are those of k_qprep, so Pq is the same bits.
+constexpr int kQpRows = 16;
+
+__global__ void __launch_bounds__(256) k_qprep_rows(const float* __restrict__ Q, int64_t nq,
+                                                    const float* __restrict__ B, int cols, int K,
+                                                    int rpad, float* __restrict__ Pq) {
+  __shared__ float As[2][kQpRows * LDT], Bs[2][BN * LDT];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * kQpRows;
+  const int srow = t >> 3, kc = (t & 7) * 4;  // staging: row t / 8 (and + 32), 4 elements
+  for (int c0 = 0; c0 < rpad; c0 += BN) {
+    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb0 = ra, rb1 = ra;
+    auto load = [&](int k0) {
+      const int kk = k0 + kc;
+      ra = make_float4(0.f, 0.f, 0.f, 0.f);
+      rb0 = ra;
+      rb1 = ra;
+      if (kk < K) {
+        if (srow < kQpRows && r0 + srow < nq) ra = *reinterpret_cast<const float4*>(Q + (r0 + srow) * (int64_t)K + kk);
+        if (c0 + srow < cols) rb0 = *reinterpret_cast<const float4*>(B + (int64_t)(c0 + srow) * K + kk);
+        if (c0 + srow + 32 < cols) rb1 = *reinterpret_cast<const float4*>(B + (int64_t)(c0 + srow + 32) * K + kk);
+      }
+    };
+    f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
+    load(0);
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += BK, buf ^= 1) {
+      if (srow < kQpRows) {
+        float* a = &As[buf][srow * LDT + kc];
+        a[0] = ra.x; a[1] = ra.y; a[2] = ra.z; a[3] = ra.w;
+      }
+      float* b0 = &Bs[buf][srow * LDT + kc];
+      b0[0] = rb0.x; b0[1] = rb0.y; b0[2] = rb0.z; b0[3] = rb0.w;
+      float* b1 = &Bs[buf][(srow + 32) * LDT + kc];
+      b1[0] = rb1.x; b1[1] = rb1.y; b1[2] = rb1.z; b1[3] = rb1.w;
+      __syncthreads();
+      if (k0 + BK < K) load(k0 + BK);
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        const int kk = ks + (l >> 4);
+        const float a = As[buf][(l & 15) * LDT + kk];
+        const float b = Bs[buf][(16 * w + (l & 15)) * LDT + kk];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 4 * (l >> 4) + v;
+      const int col = c0 + 16 * w + (l & 15);
+      if (col < rpad && row < nq) Pq[row * rpad + col] = acc[v];
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- pivots
 // Entry choice by the nearest pivot, in two stages.
 //
@@ -332,6 +392,124 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
   }
 }
 
+// The same scores and candidates for long vectors (the query does not fit in
+// registers), with the operands staged through LDS: a workgroup of four
+// waves owns 64 queries and one pivot range, walked in passes of 256 pivots
+// (wave w takes pivots 64 w .. 64 w + 63 of a pass).  Per 32-wide k-step the
+// workgroup stages the 64 query rows (rounded to bf16 on the way) and the
+// 256 pivot rows once, double buffered so that the next step's global loads
+// are in flight during the current step's 16 MFMAs per wave; every wave
+// reads its four query and four pivot fragments from LDS.  The tiles
+// accumulate their k-steps in ascending order with the same operands as
+// k_pivot_scores, so scores, stripe minima and candidates are the same
+// bits.  At the end the four waves' stripe minima (stripe = pivot column
+// mod 16 within the range) are combined through LDS.
+constexpr int kPlQ = 64;     // queries per workgroup
+constexpr int kPlP = 256;    // pivots per pass
+constexpr int kPlRow = 40;   // LDS row pitch in bf16 elements (32 + 8)
+
+__global__ void __launch_bounds__(256) k_pivot_scores_lds(const float* __restrict__ Q, int64_t nq, int m,
+                                                          const __bf16* __restrict__ PB,
+                                                          const float* __restrict__ pnorm, int npiv,
+                                                          int kpad, int range,
+                                                          uint64_t* __restrict__ cand) {
+  __shared__ __align__(16) __bf16 sA[2][kPlQ * kPlRow];
+  __shared__ __align__(16) __bf16 sB[2][kPlP * kPlRow];
+  const int tid = threadIdx.x;
+  const int w = uniform_i(tid >> 6), l = tid & 63, lr = l & 15, lk = 8 * (l >> 4);
+  const int64_t q0 = (int64_t)blockIdx.x * kPlQ;
+  const int split = blockIdx.y;
+  const int c_beg = split * range;
+  const int ksteps = kpad / 32;
+  // staging roles: query row tid / 4, elements 8 (tid % 4) .. +8 of the
+  // k-step; pivot row tid of the pass, all 32 elements of the k-step
+  const int arow = tid >> 2, acol = 8 * (tid & 3);
+  const int64_t aq = q0 + arow;
+  uint64_t best[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) best[i][v] = ~0ull;
+  for (int pass = 0; pass < range; pass += kPlP) {
+    const bool brow_ok = pass + tid < range;
+    const __bf16* bsrc = PB + (int64_t)(c_beg + pass + (brow_ok ? tid : 0)) * kpad;
+    float4 ra0, ra1;
+    uint4 rb[4];
+    auto load_step = [&](int ks) {
+      const int k = 32 * ks + acol;
+      ra0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      ra1 = ra0;
+      if (aq < nq) {
+        const float* src = Q + aq * (int64_t)m;
+        if (k < m) ra0 = *reinterpret_cast<const float4*>(src + k);
+        if (k + 4 < m) ra1 = *reinterpret_cast<const float4*>(src + k + 4);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        rb[c] = brow_ok ? *reinterpret_cast<const uint4*>(bsrc + 32 * ks + 8 * c) : make_uint4(0u, 0u, 0u, 0u);
+    };
+    f4v acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    load_step(0);
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int buf = ks & 1;
+      {
+        b8v av;
+        av[0] = (__bf16)ra0.x; av[1] = (__bf16)ra0.y; av[2] = (__bf16)ra0.z; av[3] = (__bf16)ra0.w;
+        av[4] = (__bf16)ra1.x; av[5] = (__bf16)ra1.y; av[6] = (__bf16)ra1.z; av[7] = (__bf16)ra1.w;
+        *reinterpret_cast<b8v*>(&sA[buf][arow * kPlRow + acol]) = av;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) *reinterpret_cast<uint4*>(&sB[buf][tid * kPlRow + 8 * c]) = rb[c];
+      }
+      __syncthreads();
+      if (ks + 1 < ksteps) load_step(ks + 1);
+      b8v a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const b8v*>(&sA[buf][(16 * i + lr) * kPlRow + lk]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[j] = *reinterpret_cast<const b8v*>(&sB[buf][(64 * w + 16 * j + lr) * kPlRow + lk]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rel = pass + 64 * w + 16 * j + lr;  // column within the range
+      if (rel < range) {
+        const int col = c_beg + rel;
+        const float pn = pnorm[col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fold_tile(acc[i][j], col, npiv, pn, best[i]);
+      }
+    }
+    __syncthreads();  // the next pass restages both buffers
+  }
+  // stripe minima of the four waves: S[row][wave][stripe]
+  uint64_t* S = reinterpret_cast<uint64_t*>(&sB[0][0]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[((16 * i + 4 * (l >> 4) + v) * 4 + w) * 16 + lr] = best[i][v];
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int row = 16 * w + 4 * it + (l >> 4);
+    uint64_t mn = S[(row * 4) * 16 + lr];
+#pragma unroll
+    for (int ww = 1; ww < 4; ++ww) {
+      const uint64_t o = S[(row * 4 + ww) * 16 + lr];
+      mn = o < mn ? o : mn;
+    }
+    const uint64_t srt = sort16(mn);
+    if (lr < kPivKeep && q0 + row < nq) cand[(q0 + row) * kPivCand + split * kPivKeep + lr] = srt;
+  }
+}
+
 // Per query (one wave): |q|^2, then (with candidates) the exact re-rank.
 // PF: float32 pivot rows [npiv][m].
 __global__ void k_qfinish(const float* __restrict__ Q, int64_t nq, int m,
@@ -424,8 +602,13 @@ hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float*
   uint64_t* cand = piv ? reinterpret_cast<uint64_t*>(scratch) : nullptr;
   if (t.r > 0 && need_pq) {
     // Pq = P q in float32 MFMA (the estimate needs full precision)
-    dim3 grid((unsigned)(rcols / BN), (unsigned)((nq + BM - 1) / BM));
-    hipLaunchKernelGGL(k_qprep, grid, dim3(256), 0, s, Q, nq, t.qprep_B, rcols, t.m, rpad, Pq);
+    if (t.m > 128) {
+      hipLaunchKernelGGL(k_qprep_rows, dim3((unsigned)((nq + kQpRows - 1) / kQpRows)), dim3(256), 0, s, Q,
+                         nq, t.qprep_B, rcols, t.m, rpad, Pq);
+    } else {
+      dim3 grid((unsigned)(rcols / BN), (unsigned)((nq + BM - 1) / BM));
+      hipLaunchKernelGGL(k_qprep, grid, dim3(256), 0, s, Q, nq, t.qprep_B, rcols, t.m, rpad, Pq);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -435,7 +618,14 @@ hipError_t launch_query_prep(const Tables& t, const float* Q, int64_t nq, float*
     const int kpad = pivot_kpad(t.m);
     const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
     const float* pn = t.piv_norm;
-    switch (kpad / 32) {
+    if (kpad > 128) {
+      // long vectors: operands staged through LDS (same candidates)
+      const dim3 g2((unsigned)((nq + kPlQ - 1) / kPlQ), (unsigned)kPivSplit);
+      hipLaunchKernelGGL(k_pivot_scores_lds, g2, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad,
+                         range, cand);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    } else switch (kpad / 32) {
       case 1: hipLaunchKernelGGL(k_pivot_scores<1>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
       case 2: hipLaunchKernelGGL(k_pivot_scores<2>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
       case 3: hipLaunchKernelGGL(k_pivot_scores<3>, grid, block, 0, s, Q, nq, t.m, t.piv_b16, pn, t.npiv, kpad, range, cand); break;
