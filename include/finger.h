@@ -311,6 +311,27 @@ FINGER_API int finger_search(const finger_tables* t, const float* queries, int64
                   int32_t* out_ids, float* out_dist, int32_t* out_counters,
                   void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * finger_search_noalloc - finger_search for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same search, with its scratch (query norms and
+ * projections, entries, queue counter, pivot candidates, visited-set spill
+ * tables, normalized queries) in a fixed device array of
+ * finger_search_noalloc_capacity() bytes (64 MiB) that the library holds on
+ * each GPU it runs on until the process ends, instead of a caller workspace.
+ * The call allocates nothing; the scratch parts that must start cleared are
+ * cleared by fill kernels on `stream` at every call.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialized by the caller.  Arguments,
+ * results and errors as finger_search, plus EOVERFLOW when the search needs
+ * more scratch than the array holds (fewer queries per call then fit).
+ * Async.
+ */
+FINGER_API size_t finger_search_noalloc_capacity(void);
+FINGER_API int finger_search_noalloc(const finger_tables* t, const float* queries, int64_t nq,
+                                     const finger_search_params* p /* host */, int32_t* out_ids,
+                                     float* out_dist, int32_t* out_counters, void* stream);
+
 /* ---------------------------------------------------------------- graph */
 
 typedef struct finger_graph_stats {

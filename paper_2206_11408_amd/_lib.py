@@ -39,7 +39,8 @@ EXPORTED = (
     "finger_adam_step", "finger_gate_targets", "finger_last_error",
     "finger_hierarchy_attach", "finger_descend", "finger_build_graph",
     "finger_mlp_backward_workspace_size", "finger_gate_calibrate", "finger_tables_export",
-    "finger_tables_import", "finger_checksum64",
+    "finger_tables_import", "finger_checksum64", "finger_search_noalloc",
+    "finger_search_noalloc_capacity",
 )
 
 
@@ -146,6 +147,10 @@ def load() -> C.CDLL:
     lib.finger_tables_export.argtypes = [vp, vp, P(sz)]
     lib.finger_tables_import.restype = C.c_int
     lib.finger_tables_import.argtypes = [vp, sz, vp, i64, i32, vp, i32, P(vp), vp]
+    lib.finger_search_noalloc.restype = C.c_int
+    lib.finger_search_noalloc.argtypes = [vp, vp, i64, P(SearchParams), vp, vp, vp, vp]
+    lib.finger_search_noalloc_capacity.restype = sz
+    lib.finger_search_noalloc_capacity.argtypes = []
     lib.finger_checksum64.restype = C.c_uint64
     lib.finger_checksum64.argtypes = [vp, sz]
     lib.finger_adam_step.restype = C.c_int

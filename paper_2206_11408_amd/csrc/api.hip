@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -525,6 +526,64 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   HIPCHK(launch_search(*t, L, s));
   if (ev1) HIPCHK(hipEventRecord(ev1, s));
   return ok();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ search without allocation
+
+namespace {
+
+// Scratch of finger_search_noalloc: a fixed array in the code object's
+// device memory, one copy per GPU, held until the process ends.  In host
+// code the name only stands in for the array; its address on a device comes
+// from hipGetSymbolAddress (once per device, with that device current) and
+// is the only form passed to kernels or fills.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FINGER_EDEVICE, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(FINGER_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return FINGER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t finger_search_noalloc_capacity(void) { return kNoAllocScratchBytes; }
+
+int finger_search_noalloc(const finger_tables* th, const float* queries, int64_t nq,
+                          const finger_search_params* p, int32_t* out_ids, float* out_dist,
+                          int32_t* out_counters, void* stream) {
+  if (th == nullptr || p == nullptr) return fail(FINGER_EINVAL, "NULL handle or params");
+  Plan pl;
+  const int st = plan_search(reinterpret_cast<const Tables*>(th), nq, p, &pl);
+  if (st != FINGER_OK) return st;
+  if (pl.total > kNoAllocScratchBytes)
+    return fail(FINGER_EOVERFLOW,
+                "the search needs %zu bytes of scratch, more than the %zu finger_search_noalloc holds "
+                "(fewer queries per call, or finger_search with a workspace)",
+                pl.total, kNoAllocScratchBytes);
+  void* ws = nullptr;
+  const int sa = scratch_address(&ws);
+  if (sa != FINGER_OK) return sa;
+  return finger_search(th, queries, nq, p, out_ids, out_dist, out_counters, ws, kNoAllocScratchBytes,
+                       stream);
 }
 
 int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, int32_t max_degree,
