@@ -393,104 +393,116 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
 }
 
 // The same scores and candidates for long vectors (the query does not fit in
-// registers), with the operands staged through LDS: a workgroup of four
-// waves owns 64 queries and one pivot range, walked in passes of 256 pivots
-// (wave w takes pivots 64 w .. 64 w + 63 of a pass).  Per 32-wide k-step the
-// workgroup stages the 64 query rows (rounded to bf16 on the way) and the
-// 256 pivot rows once, double buffered so that the next step's global loads
-// are in flight during the current step's 16 MFMAs per wave; every wave
-// reads its four query and four pivot fragments from LDS.  The tiles
-// accumulate their k-steps in ascending order with the same operands as
+// registers), for a workgroup of four waves that owns 64 queries and one
+// pivot range, walked in passes of 256 pivots (wave w takes pivots 64 w ..
+// 64 w + 63 of a pass).  Per 32-wide k-step the workgroup stages the 64
+// query rows once through LDS (rounded to bf16 on the way), and each wave
+// reads its own pivot fragments straight from memory (the waves' pivots are
+// disjoint); both are loaded one step ahead, so the next step's loads are in
+// flight during the current step's 16 MFMAs per wave.  The tiles accumulate
+// their k-steps in ascending order with the same operands as
 // k_pivot_scores, so scores, stripe minima and candidates are the same
 // bits.  At the end the four waves' stripe minima (stripe = pivot column
 // mod 16 within the range) are combined through LDS.
 constexpr int kPlQ = 64;     // queries per workgroup
 constexpr int kPlP = 256;    // pivots per pass
-constexpr int kPlRow = 40;   // LDS row pitch in bf16 elements (32 + 8)
+constexpr int kPlRow = 40;   // LDS row pitch of the query slab in bf16 elements (32 + 8)
 
 __global__ void __launch_bounds__(256) k_pivot_scores_lds(const float* __restrict__ Q, int64_t nq, int m,
                                                           const __bf16* __restrict__ PB,
                                                           const float* __restrict__ pnorm, int npiv,
                                                           int kpad, int range,
                                                           uint64_t* __restrict__ cand) {
-  __shared__ __align__(16) __bf16 sA[2][kPlQ * kPlRow];
-  __shared__ __align__(16) __bf16 sB[2][kPlP * kPlRow];
+  // query slabs (2 x 64 x 40 bf16) during the k loop, then the stripe
+  // minima (64 rows x 4 waves x 16 stripes)
+  __shared__ __align__(16) uint64_t lds_raw[kPlQ * 4 * 16];
+  __bf16* sA = reinterpret_cast<__bf16*>(lds_raw);
+  static_assert(2 * kPlQ * kPlRow * 2 <= kPlQ * 4 * 16 * 8, "slabs fit the stripe area");
   const int tid = threadIdx.x;
   const int w = uniform_i(tid >> 6), l = tid & 63, lr = l & 15, lk = 8 * (l >> 4);
   const int64_t q0 = (int64_t)blockIdx.x * kPlQ;
   const int split = blockIdx.y;
   const int c_beg = split * range;
   const int ksteps = kpad / 32;
-  // staging roles: query row tid / 4, elements 8 (tid % 4) .. +8 of the
-  // k-step; pivot row tid of the pass, all 32 elements of the k-step
+  // staging role: query row tid / 4, elements 8 (tid % 4) .. +8 of the k-step
   const int arow = tid >> 2, acol = 8 * (tid & 3);
   const int64_t aq = q0 + arow;
+  const float* asrc = Q + (aq < nq ? aq : 0) * (int64_t)m;
   uint64_t best[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) best[i][v] = ~0ull;
+  const b8v zero8 = b8v{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
+                        (__bf16)0.f, (__bf16)0.f};
   for (int pass = 0; pass < range; pass += kPlP) {
-    const bool brow_ok = pass + tid < range;
-    const __bf16* bsrc = PB + (int64_t)(c_beg + pass + (brow_ok ? tid : 0)) * kpad;
+    // this lane's pivot row of each of the wave's four tiles
+    const __bf16* brow[4];
+    bool bok[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rel = pass + 64 * w + 16 * j + lr;
+      bok[j] = rel < range;
+      brow[j] = PB + (int64_t)(c_beg + (bok[j] ? rel : 0)) * kpad + lk;
+    }
     float4 ra0, ra1;
-    uint4 rb[4];
-    auto load_step = [&](int ks) {
+    b8v bcur[4], bnxt[4];
+    auto load_a = [&](int ks) {
       const int k = 32 * ks + acol;
       ra0 = make_float4(0.f, 0.f, 0.f, 0.f);
       ra1 = ra0;
       if (aq < nq) {
-        const float* src = Q + aq * (int64_t)m;
-        if (k < m) ra0 = *reinterpret_cast<const float4*>(src + k);
-        if (k + 4 < m) ra1 = *reinterpret_cast<const float4*>(src + k + 4);
+        if (k < m) ra0 = *reinterpret_cast<const float4*>(asrc + k);
+        if (k + 4 < m) ra1 = *reinterpret_cast<const float4*>(asrc + k + 4);
       }
+    };
+    auto load_b = [&](int ks, b8v* dst) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        rb[c] = brow_ok ? *reinterpret_cast<const uint4*>(bsrc + 32 * ks + 8 * c) : make_uint4(0u, 0u, 0u, 0u);
+      for (int j = 0; j < 4; ++j) dst[j] = bok[j] ? *reinterpret_cast<const b8v*>(brow[j] + 32 * ks) : zero8;
     };
     f4v acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
-    load_step(0);
+    load_a(0);
+    load_b(0, bcur);
     for (int ks = 0; ks < ksteps; ++ks) {
-      const int buf = ks & 1;
+      __bf16* slab = sA + (ks & 1) * (kPlQ * kPlRow);
       {
         b8v av;
         av[0] = (__bf16)ra0.x; av[1] = (__bf16)ra0.y; av[2] = (__bf16)ra0.z; av[3] = (__bf16)ra0.w;
         av[4] = (__bf16)ra1.x; av[5] = (__bf16)ra1.y; av[6] = (__bf16)ra1.z; av[7] = (__bf16)ra1.w;
-        *reinterpret_cast<b8v*>(&sA[buf][arow * kPlRow + acol]) = av;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) *reinterpret_cast<uint4*>(&sB[buf][tid * kPlRow + 8 * c]) = rb[c];
+        *reinterpret_cast<b8v*>(slab + arow * kPlRow + acol) = av;
       }
       __syncthreads();
-      if (ks + 1 < ksteps) load_step(ks + 1);
-      b8v a[4], b[4];
+      if (ks + 1 < ksteps) {
+        load_a(ks + 1);
+        load_b(ks + 1, bnxt);
+      }
+      b8v a[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const b8v*>(&sA[buf][(16 * i + lr) * kPlRow + lk]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        b[j] = *reinterpret_cast<const b8v*>(&sB[buf][(64 * w + 16 * j + lr) * kPlRow + lk]);
+      for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const b8v*>(slab + (16 * i + lr) * kPlRow + lk);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bcur[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bcur[j] = bnxt[j];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int rel = pass + 64 * w + 16 * j + lr;  // column within the range
-      if (rel < range) {
-        const int col = c_beg + rel;
+      if (bok[j]) {
+        const int col = c_beg + pass + 64 * w + 16 * j + lr;
         const float pn = pnorm[col];
 #pragma unroll
         for (int i = 0; i < 4; ++i) fold_tile(acc[i][j], col, npiv, pn, best[i]);
       }
     }
-    __syncthreads();  // the next pass restages both buffers
+    __syncthreads();  // the next pass restages the slabs
   }
   // stripe minima of the four waves: S[row][wave][stripe]
-  uint64_t* S = reinterpret_cast<uint64_t*>(&sB[0][0]);
+  uint64_t* S = lds_raw;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
