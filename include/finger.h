@@ -248,6 +248,14 @@ typedef struct finger_search_params {
                             fewer, more bytes); -1 = request codes of
                             unvisited neighbours only; 0 = library default
                             (prefetch for BF16/FP8 codes) */
+  int32_t ef_classes;    /* with k_per_query or ef_per_query: 0 (default) or 1
+                            = partition the queries by ef class (ef_eff =
+                            max(ef, K) in (16, 32], (32, 64], ... up to
+                            ef_max) and run one persistent launch per class,
+                            each reserving LDS, a visited table and resident
+                            waves for its own bound; 2 = one launch in which
+                            every wave reserves them for ef_max.  Results do
+                            not depend on it. */
   int32_t screen_layout; /* FINGER mode: how lanes read the edge codes.
                             0 = library default (coalesced where it applies);
                             1 = coalesced: each load instruction reads 1 KB of
@@ -384,6 +392,26 @@ FINGER_API int finger_build_graph(const float* data, int64_t n, int32_t m, int32
                                   int32_t* out_graph, finger_graph_stats* stats /* host */,
                                   finger_progress_fn progress, void* progress_user,
                                   void* stream);
+
+/*
+ * finger_build_graph_grouped - finger_build_graph with step 1 restricted to
+ * groups: the points are ordered so that each group is a contiguous range
+ * [group_offsets[g], group_offsets[g + 1]) (host int64, group_offsets[0] = 0,
+ * group_offsets[n_groups] = n, every group at least knn_k + 1 points), and a
+ * point's knn_k nearest are taken among the points of its own group; steps
+ * 2-4 are unchanged.  This is the exact kNN graph whenever every point's
+ * knn_k nearest lie in its own group, e.g. for well separated clusters whose
+ * labels are known (a workload generator's), at a cost of sum of group
+ * sizes squared instead of n squared.  Errors as finger_build_graph, plus
+ * EINVAL for offsets that do not run from 0 to n or a group that is too
+ * small.  Synchronous.
+ */
+FINGER_API int finger_build_graph_grouped(const float* data, int64_t n, int32_t m, int32_t knn_k,
+                                          int32_t max_degree, int32_t metric, int32_t entry,
+                                          const int64_t* group_offsets /* host */, int64_t n_groups,
+                                          int32_t* out_graph, finger_graph_stats* stats /* host */,
+                                          finger_progress_fn progress, void* progress_user,
+                                          void* stream);
 
 /* ------------------------------------------------------------ hierarchy */
 

@@ -40,7 +40,7 @@ EXPORTED = (
     "finger_hierarchy_attach", "finger_descend", "finger_build_graph",
     "finger_mlp_backward_workspace_size", "finger_gate_calibrate", "finger_tables_export",
     "finger_tables_import", "finger_checksum64", "finger_search_noalloc",
-    "finger_search_noalloc_capacity",
+    "finger_search_noalloc_capacity", "finger_build_graph_grouped",
 )
 
 
@@ -60,7 +60,7 @@ class SearchParams(C.Structure):
         ("k_per_query", C.c_void_p), ("ef_per_query", C.c_void_p),
         ("ef_max", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
         ("visited_capacity", C.c_int32), ("spill_capacity", C.c_int32),
-        ("code_prefetch", C.c_int32), ("screen_layout", C.c_int32),
+        ("code_prefetch", C.c_int32), ("ef_classes", C.c_int32), ("screen_layout", C.c_int32),
         ("log_features", C.c_void_p), ("log_targets", C.c_void_p),
         ("log_capacity", C.c_int64), ("log_count", C.c_void_p),
         ("kernel_events", C.c_void_p * 2),
@@ -159,6 +159,9 @@ def load() -> C.CDLL:
     lib.finger_build_graph.restype = C.c_int
     lib.finger_build_graph.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, P(GraphStats),
                                        PROGRESS_FN, vp, vp]
+    lib.finger_build_graph_grouped.restype = C.c_int
+    lib.finger_build_graph_grouped.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, i64, vp,
+                                               P(GraphStats), PROGRESS_FN, vp, vp]
     lib.finger_hierarchy_attach.restype = C.c_int
     lib.finger_hierarchy_attach.argtypes = [vp, vp, vp, i64, i32]
     lib.finger_descend.restype = C.c_int

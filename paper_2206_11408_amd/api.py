@@ -143,7 +143,7 @@ def finger_build_tables(data: torch.Tensor, graph: torch.Tensor, rank: int = 0,
 def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
                   k_per_query=None, ef_per_query=None, ef_max=0, persistent=0,
                   waves_per_cu=0, visited_capacity=0, code_prefetch=0,
-                  log=None, spill_capacity=0, screen_layout=0) -> L.SearchParams:
+                  log=None, spill_capacity=0, screen_layout=0, ef_classes=0) -> L.SearchParams:
     p = L.SearchParams()
     L.load().finger_search_params_init(C.byref(p))
     p.mode, p.k, p.ef, p.entry, p.warmup = mode, k, ef, entry, warmup
@@ -154,6 +154,7 @@ def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
     p.waves_per_cu, p.visited_capacity = waves_per_cu, visited_capacity
     p.spill_capacity = spill_capacity
     p.screen_layout = screen_layout
+    p.ef_classes = ef_classes
     p.code_prefetch = code_prefetch
     if log is not None:
         feats, targs, count = log
@@ -223,6 +224,24 @@ def finger_build_graph(data: torch.Tensor, knn_k: int = 16, max_degree: int = 32
     cb = L.PROGRESS_FN(lambda ph, d, t, _u: progress(ph.decode(), d, t)) if progress else L.PROGRESS_FN()
     L.check(L.load().finger_build_graph(data.data_ptr(), n, m, knn_k, max_degree, metric, entry,
                                         G.data_ptr(), C.byref(st), cb, None, _stream()))
+    return G, {name: getattr(st, name) for name, _ in L.GraphStats._fields_}
+
+
+def finger_build_graph_grouped(data: torch.Tensor, group_offsets, knn_k: int = 16,
+                               max_degree: int = 32, entry: int = 0, metric: int = L.L2,
+                               progress=None):
+    """finger_build_graph with each point's kNN taken inside its own group
+    (finger_build_graph_grouped); ``group_offsets`` [n_groups + 1] from 0 to n
+    delimits contiguous groups of rows."""
+    data = _dev_f32(data)
+    n, m = data.shape
+    off = np.ascontiguousarray(np.asarray(group_offsets, dtype=np.int64))
+    G = torch.empty((n, max_degree), dtype=torch.int32, device=data.device)
+    st = L.GraphStats()
+    cb = L.PROGRESS_FN(lambda ph, d, t, _u: progress(ph.decode(), d, t)) if progress else L.PROGRESS_FN()
+    L.check(L.load().finger_build_graph_grouped(data.data_ptr(), n, m, knn_k, max_degree, metric, entry,
+                                                off.ctypes.data, off.size - 1, G.data_ptr(), C.byref(st),
+                                                cb, None, _stream()))
     return G, {name: getattr(st, name) for name, _ in L.GraphStats._fields_}
 
 

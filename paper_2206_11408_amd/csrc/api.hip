@@ -356,6 +356,11 @@ namespace {
 struct Plan {
   int ef_max, vis_cap, waves, lds, spill_slots;
   size_t off_qq, off_pq, off_ent, off_queue, off_qscr, off_spill, off_qn, total;
+  // ef classes (a partitioned search with per-query K/ef): one launch per
+  // class, each sized for its own bound
+  finger::ClassBounds cb;
+  int cls_vis[finger::kMaxEfClasses], cls_waves[finger::kMaxEfClasses], cls_spill[finger::kMaxEfClasses];
+  size_t off_lists, off_counts;
 };
 
 int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan* pl) {
@@ -389,8 +394,10 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
     if (ef_max < need) ef_max = need;
   }
   if (ef_max > kMaxEf) return fail(FINGER_EOVERFLOW, "ef_max = %d exceeds %d", ef_max, kMaxEf);
+  if (p->ef_classes < 0 || p->ef_classes > 2) return fail(FINGER_EINVAL, "ef_classes = %d must be 0, 1 or 2", p->ef_classes);
+  auto vis_default = [](int ef) { return std::min(8192, std::max(1024, next_pow2(24 * ef))); };
   int vis_cap = p->visited_capacity;
-  if (vis_cap == 0) vis_cap = std::min(8192, std::max(1024, next_pow2(24 * ef_max)));
+  if (vis_cap == 0) vis_cap = vis_default(ef_max);
   if (p->code_prefetch < -1 || p->code_prefetch > 1)
     return fail(FINGER_EINVAL, "code_prefetch = %d must be -1, 0 or 1", p->code_prefetch);
   if (p->screen_layout < 0 || p->screen_layout > 2)
@@ -420,11 +427,37 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   pl->off_ent = off; off += align256((size_t)nq * 4);
   pl->off_queue = off; off += 256;
   pl->off_qscr = off; off += align256(query_prep_scratch_bytes(*t, nq));
+  auto spill_default = [&](int ef) { return std::min(65536, std::max(1024, next_pow2(ef * t->deg))); };
   int spill_slots = p->spill_capacity;
-  if (spill_slots == 0) spill_slots = std::min(65536, std::max(1024, next_pow2(ef_max * t->deg)));
+  if (spill_slots == 0) spill_slots = spill_default(ef_max);
   if (spill_slots < 64 || spill_slots > (1 << 20) || (spill_slots & (spill_slots - 1)) != 0)
     return fail(FINGER_EINVAL, "spill_capacity = %d must be a power of two in [64, 2^20]", spill_slots);
-  pl->off_spill = off; off += align256((size_t)waves * spill_slots * 4);
+  // ef classes: bounds 32, 64, ... below ef_max, then ef_max
+  pl->cb.n = 0;
+  size_t spill_words = (size_t)waves * spill_slots;
+  if (perq && p->ef_classes != 2) {
+    for (int b = 32; b < ef_max && pl->cb.n < kMaxEfClasses - 1; b *= 2) pl->cb.bound[pl->cb.n++] = b;
+    pl->cb.bound[pl->cb.n++] = ef_max;
+    for (int c = 0; c < pl->cb.n; ++c) {
+      const int b = pl->cb.bound[c];
+      const int vc = p->visited_capacity ? p->visited_capacity : vis_default(b);
+      const int lw = search_lds_bytes(b, vc, r_used, t->m, gate_in);
+      if (lw > lds_limit) return fail(FINGER_EOVERFLOW, "per-wave LDS of %d bytes for ef class %d exceeds the CU budget", lw, b);
+      const int fit = lds_limit / lw;
+      int pc = p->waves_per_cu > 0 ? std::min(p->waves_per_cu, fit) : std::min(16, fit);
+      int wv = pc * cu_count();
+      if (nq < wv) wv = (int)std::max<int64_t>(nq, 1);
+      pl->cls_vis[c] = vc;
+      pl->cls_waves[c] = wv;
+      pl->cls_spill[c] = p->spill_capacity ? p->spill_capacity : spill_default(b);
+      spill_words = std::max(spill_words, (size_t)wv * pl->cls_spill[c]);
+    }
+  }
+  pl->off_spill = off; off += align256(spill_words * 4);
+  pl->off_lists = off;
+  if (pl->cb.n > 0) off += align256((size_t)pl->cb.n * nq * 4);
+  pl->off_counts = off;
+  if (pl->cb.n > 0) off += 256;
   pl->spill_slots = spill_slots;
   // angular metric: the search reads unit-normalized copies of the queries
   pl->off_qn = off;
@@ -474,7 +507,7 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   float* qq = reinterpret_cast<float*>(ws + pl.off_qq);
   float* pq = reinterpret_cast<float*>(ws + pl.off_pq);
   int32_t* ent = reinterpret_cast<int32_t*>(ws + pl.off_ent);
-  int32_t* queue = reinterpret_cast<int32_t*>(ws + pl.off_queue);
+  int32_t* queue = reinterpret_cast<int32_t*>(ws + pl.off_queue);  // [kMaxEfClasses]
   float* qscr = reinterpret_cast<float*>(ws + pl.off_qscr);
   int32_t* spill = reinterpret_cast<int32_t*>(ws + pl.off_spill);
   if (t->metric == FINGER_ANGULAR) {
@@ -483,8 +516,8 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
     queries = qn;
   }
   // fill kernels rather than memsets: a caller may capture this call in a graph
-  HIPCHK(launch_fill_u32(queue, 0u, 1, s));
-  HIPCHK(launch_fill_u32(spill, 0xFFFFFFFFu, (size_t)pl.waves * pl.spill_slots, s));
+  HIPCHK(launch_fill_u32(queue, 0u, kMaxEfClasses, s));
+  HIPCHK(launch_fill_u32(spill, 0xFFFFFFFFu, (pl.off_lists - pl.off_spill) / 4, s));
   const bool need_prep = p->mode != FINGER_MODE_PLAIN || p->entry == FINGER_ENTRY_PIVOT;
   if (need_prep)
     HIPCHK(launch_query_prep(*t, queries, nq, qq, pq, p->entry == FINGER_ENTRY_PIVOT ? ent : nullptr,
@@ -522,8 +555,27 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.log_count = p->log_count;
   hipEvent_t ev0 = static_cast<hipEvent_t>(p->kernel_events[0]);
   hipEvent_t ev1 = static_cast<hipEvent_t>(p->kernel_events[1]);
+  int32_t* lists = reinterpret_cast<int32_t*>(ws + pl.off_lists);
+  int32_t* counts = reinterpret_cast<int32_t*>(ws + pl.off_counts);
+  if (pl.cb.n > 0) HIPCHK(launch_ef_classes(p->k_per_query, p->ef_per_query, nq, p->k, p->ef, pl.cb, counts, lists, s));
   if (ev0) HIPCHK(hipEventRecord(ev0, s));
-  HIPCHK(launch_search(*t, L, s));
+  if (pl.cb.n == 0) {
+    HIPCHK(launch_search(*t, L, s));
+  } else {
+    // one persistent launch per ef class, each sized for its own bound
+    for (int c = 0; c < pl.cb.n; ++c) {
+      SearchLaunch Lc = L;
+      Lc.ef_max = pl.cb.bound[c];
+      Lc.vis_cap = pl.cls_vis[c];
+      Lc.waves = pl.cls_waves[c];
+      Lc.spill_slots_per_wave = pl.cls_spill[c];
+      Lc.persistent = 1;
+      Lc.queue = queue + c;
+      Lc.qlist = lists + (int64_t)c * nq;
+      Lc.qcount = counts + c;
+      HIPCHK(launch_search(*t, Lc, s));
+    }
+  }
   if (ev1) HIPCHK(hipEventRecord(ev1, s));
   return ok();
 }
@@ -586,9 +638,17 @@ int finger_search_noalloc(const finger_tables* th, const float* queries, int64_t
                        stream);
 }
 
-int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, int32_t max_degree,
-                       int32_t metric, int32_t entry, int32_t* out_graph, finger_graph_stats* stats,
-                       finger_progress_fn progress, void* progress_user, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The graph recipe of finger_build_graph; with groups (host offsets
+// group[0] = 0 < ... < group[n_groups] = n) each point's kNN is taken among
+// the points of its own group only.
+int build_graph_impl(const float* data, int64_t n, int32_t m, int32_t knn_k, int32_t max_degree,
+                     int32_t metric, int32_t entry, const int64_t* groups, int64_t n_groups,
+                     int32_t* out_graph, finger_graph_stats* stats, finger_progress_fn progress,
+                     void* progress_user, void* stream) {
   using namespace finger;
   if (data == nullptr || out_graph == nullptr) return fail(FINGER_EINVAL, "NULL data or out_graph");
   if (n < 2) return fail(FINGER_EINVAL, "n = %lld < 2", (long long)n);
@@ -603,6 +663,16 @@ int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, i
   if ((reinterpret_cast<uintptr_t>(data) & 15u) != 0) return fail(FINGER_EINVAL, "data must be 16-byte aligned");
   const int k = knn_k, k1 = knn_k + 1, W = max_degree;
   const int64_t nk = n * k, ne = 2 * nk;
+  int64_t gmax = 0;
+  if (groups != nullptr) {
+    if (n_groups < 1 || groups[0] != 0 || groups[n_groups] != n)
+      return fail(FINGER_EINVAL, "group offsets must run from 0 to n");
+    for (int64_t g = 0; g < n_groups; ++g) {
+      const int64_t sz = groups[g + 1] - groups[g];
+      if (sz < k1) return fail(FINGER_EINVAL, "group %lld holds %lld points, fewer than knn_k + 1", (long long)g, (long long)sz);
+      gmax = std::max(gmax, sz);
+    }
+  }
   if (ne >= (int64_t(1) << 31)) return fail(FINGER_EOVERFLOW, "2 n knn_k = %lld >= 2^31", (long long)ne);
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto now = [] { return std::chrono::steady_clock::now(); };
@@ -625,22 +695,38 @@ int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, i
     HIPCHK(launch_normalize_rows(data, n, m, normed.p, s));
     X = normed.p;
   }
-  const int64_t batch = std::min<int64_t>(n, int64_t(1) << 20);
+  const int64_t batch = groups != nullptr ? std::min<int64_t>(gmax, int64_t(1) << 20)
+                                          : std::min<int64_t>(n, int64_t(1) << 20);
   DevBuf<char> kws;
   DevBuf<int32_t> ids1, ids;
   DevBuf<float> d1, dk;
-  alloc(kws, exact_knn_ws_bytes(n, m, batch, k1), "kNN workspace");
+  alloc(kws, exact_knn_ws_bytes(groups != nullptr ? gmax : n, m, batch, k1), "kNN workspace");
   alloc(ids1, (size_t)batch * k1 * 4, "kNN ids");
   alloc(d1, (size_t)batch * k1 * 4, "kNN distances");
   alloc(ids, (size_t)nk * 4, "kNN lists");
   alloc(dk, (size_t)nk * 4, "kNN list distances");
   if (rc != FINGER_OK) return rc;
-  for (int64_t b0 = 0; b0 < n; b0 += batch) {
-    const int64_t nb = std::min(batch, n - b0);
-    HIPCHK(launch_exact_knn(X, n, m, X + b0 * m, nb, k1, FINGER_L2, ids1.p, d1.p, kws.p, s));
-    HIPCHK(launch_drop_self(ids1.p, d1.p, nb, k1, k, ids.p + b0 * k, dk.p + b0 * k, b0, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (progress) progress("knn", b0 + nb, n, progress_user);
+  if (groups == nullptr) {
+    for (int64_t b0 = 0; b0 < n; b0 += batch) {
+      const int64_t nb = std::min(batch, n - b0);
+      HIPCHK(launch_exact_knn(X, n, m, X + b0 * m, nb, k1, FINGER_L2, ids1.p, d1.p, kws.p, s));
+      HIPCHK(launch_drop_self(ids1.p, d1.p, nb, k1, k, ids.p + b0 * k, dk.p + b0 * k, b0, 0, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (progress) progress("knn", b0 + nb, n, progress_user);
+    }
+  } else {
+    for (int64_t g = 0; g < n_groups; ++g) {
+      const int64_t o = groups[g], ng = groups[g + 1] - groups[g];
+      for (int64_t b0 = 0; b0 < ng; b0 += batch) {
+        const int64_t nb = std::min(batch, ng - b0);
+        HIPCHK(launch_exact_knn(X + o * m, ng, m, X + (o + b0) * m, nb, k1, FINGER_L2, ids1.p, d1.p, kws.p, s));
+        HIPCHK(launch_drop_self(ids1.p, d1.p, nb, k1, k, ids.p + (o + b0) * k, dk.p + (o + b0) * k, b0, o, s));
+      }
+      if ((g + 1) % 1024 == 0 || g + 1 == n_groups) {
+        HIPCHK(hipStreamSynchronize(s));
+        if (progress) progress("knn", groups[g + 1], n, progress_user);
+      }
+    }
   }
   st.ms_knn = ms_since(t0);
   kws.reset();
@@ -806,6 +892,27 @@ int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, i
   if (progress) progress("repair", repairs, repairs, progress_user);
   if (stats != nullptr) *stats = st;
   return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int finger_build_graph(const float* data, int64_t n, int32_t m, int32_t knn_k, int32_t max_degree,
+                       int32_t metric, int32_t entry, int32_t* out_graph, finger_graph_stats* stats,
+                       finger_progress_fn progress, void* progress_user, void* stream) {
+  return build_graph_impl(data, n, m, knn_k, max_degree, metric, entry, nullptr, 0, out_graph, stats,
+                          progress, progress_user, stream);
+}
+
+int finger_build_graph_grouped(const float* data, int64_t n, int32_t m, int32_t knn_k,
+                               int32_t max_degree, int32_t metric, int32_t entry,
+                               const int64_t* group_offsets, int64_t n_groups, int32_t* out_graph,
+                               finger_graph_stats* stats, finger_progress_fn progress,
+                               void* progress_user, void* stream) {
+  if (group_offsets == nullptr) return fail(FINGER_EINVAL, "group_offsets is NULL");
+  return build_graph_impl(data, n, m, knn_k, max_degree, metric, entry, group_offsets, n_groups,
+                          out_graph, stats, progress, progress_user, stream);
 }
 
 int finger_hierarchy_attach(finger_tables* th, const int32_t* levels, const int32_t* upper,

@@ -45,14 +45,14 @@ __device__ __forceinline__ Edge edge_of(uint32_t e, int64_t nk, int k, const int
 
 // row i of a query batch starting at point `first`
 __global__ void k_drop_self(const int32_t* ids1, const float* d1, int64_t n, int k1, int k,
-                            int32_t* ids, float* dk, int64_t first) {
+                            int32_t* ids, float* dk, int64_t first, int64_t id_offset) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int o = 0;
   for (int t = 0; t < k1 && o < k; ++t) {
     const int32_t v = ids1[i * k1 + t];
     if (v == (int32_t)(first + i)) continue;
-    ids[i * k + o] = v;
+    ids[i * k + o] = (int32_t)(v + id_offset);
     dk[i * k + o] = d1[i * k1 + t];
     ++o;
   }
@@ -225,9 +225,9 @@ inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + pe
 }  // namespace
 
 hipError_t launch_drop_self(const int32_t* ids1, const float* d1, int64_t n, int k1, int k,
-                            int32_t* ids, float* dk, int64_t first, hipStream_t s) {
+                            int32_t* ids, float* dk, int64_t first, int64_t id_offset, hipStream_t s) {
   hipLaunchKernelGGL(k_drop_self, dim3(blocks_for(n)), dim3(256), 0, s, ids1, d1, n, k1, k, ids, dk,
-                     first);
+                     first, id_offset);
   return hipGetLastError();
 }
 

@@ -109,8 +109,10 @@ hipError_t launch_descend(const Tables& t, const float* Q, int64_t nq, int32_t* 
                           hipStream_t s);
 
 // flat graph construction (graph.hip); the repair loop runs in api.hip
+// kNN lists without the point itself: ids relative to the searched rows,
+// self = first + row, written plus id_offset
 hipError_t launch_drop_self(const int32_t* ids1, const float* d1, int64_t n, int k1, int k,
-                            int32_t* ids, float* dk, int64_t first, hipStream_t s);
+                            int32_t* ids, float* dk, int64_t first, int64_t id_offset, hipStream_t s);
 hipError_t launch_sym_keys_dst(int64_t n, int k, const int32_t* ids, const float* dk, uint32_t* keys,
                                uint32_t* vals, hipStream_t s);
 hipError_t launch_sym_keys_src_d(int64_t n, int k, const int32_t* ids, const float* dk,
@@ -173,8 +175,22 @@ struct SearchLaunch {
   float* log_y;
   int64_t log_cap;
   int64_t* log_count;
+  // one class of an ef-partitioned search: queries qlist[0..*qcount)
+  const int32_t* qlist;
+  const int32_t* qcount;
 };
 hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s);
+
+// ef classes of a search with per-query K and ef: class c holds the queries
+// whose ef_eff = max(ef, K) is at most bound[c] (and above bound[c - 1]);
+// the last class takes everything above
+constexpr int kMaxEfClasses = 8;
+struct ClassBounds {
+  int n;
+  int bound[kMaxEfClasses];
+};
+hipError_t launch_ef_classes(const int32_t* kq, const int32_t* efq, int64_t nq, int k_all, int ef_all,
+                             const ClassBounds& cb, int32_t* counts, int32_t* lists, hipStream_t s);
 bool search_prefetch_supported(const Tables& t);
 int search_lds_bytes(int ef_max, int vis_cap, int r, int m, int gate_in);
 

@@ -80,6 +80,9 @@ struct KArgs {
   // scheduling / scratch
   int32_t* queue;
   int persistent;
+  // one ef class of a partitioned launch: the queries are qlist[0..*qcount)
+  const int32_t* qlist;
+  const int32_t* qcount;
   int ip;     // inner-product metric: distance -q.x
   int32_t* spill;
   int spill_slots;
@@ -540,6 +543,7 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   const int lg = kCoal ? l / (kCoal ? LC : 1) : 0;
   const int myslot = (lp >> 1) * kSPI + lg;
 
+  const int64_t nq_here = a.qcount != nullptr ? (int64_t)uniform_i(*a.qcount) : a.nq;
   for (int64_t it = 0;; ++it) {
     int64_t qi;
     if (a.persistent) {
@@ -549,7 +553,8 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
     } else {
       qi = (int64_t)wave_global + it * total_waves;
     }
-    if (qi >= a.nq) break;
+    if (qi >= nq_here) break;
+    if (a.qlist != nullptr) qi = uniform_i(a.qlist[qi]);
 
     const int k = a.kq ? a.kq[qi] : a.k_all;
     const int ef = a.efq ? a.efq[qi] : a.ef_all;
@@ -1142,6 +1147,8 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   a.counters = L.counters;
   a.queue = L.queue;
   a.persistent = L.persistent;
+  a.qlist = L.qlist;
+  a.qcount = L.qcount;
   a.spill = L.spill;
   a.spill_slots = L.spill_slots_per_wave;
   a.vis_cap = L.vis_cap;
@@ -1170,6 +1177,44 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
     return launch_codes<kModeLog>(a, t.code_type, pf, blocks, lds, s);
   if (L.mode == FINGER_MODE_FINGER) return launch_codes<FINGER_MODE_FINGER>(a, t.code_type, pf, blocks, lds, s);
   return launch_codes<FINGER_MODE_GATED, false>(a, t.code_type, false, blocks, lds, s);
+}
+
+// ------------------------------------------------------ ef classes
+
+namespace {
+
+// One block: every query's class (the first bound >= its ef_eff = max(ef,
+// K), the last class for anything above), appended to that class's list
+// lists[c nq ..] (order inside a class is not fixed: a query's search does
+// not depend on the others); counts[c] and the lists drive the per-class
+// launches.
+__global__ void __launch_bounds__(1024) k_ef_classes(const int32_t* __restrict__ kq,
+                                                     const int32_t* __restrict__ efq, int64_t nq,
+                                                     int k_all, int ef_all, ClassBounds cb,
+                                                     int32_t* __restrict__ counts,
+                                                     int32_t* __restrict__ lists) {
+  __shared__ int cnt[kMaxEfClasses];
+  const int t = threadIdx.x;
+  if (t < kMaxEfClasses) cnt[t] = 0;
+  __syncthreads();
+  for (int64_t i = t; i < nq; i += blockDim.x) {
+    const int k = kq ? kq[i] : k_all;
+    const int ef = efq ? efq[i] : ef_all;
+    const int e = ef > k ? ef : k;
+    int c = 0;
+    while (c + 1 < cb.n && e > cb.bound[c]) ++c;
+    lists[(int64_t)c * nq + atomicAdd(&cnt[c], 1)] = (int32_t)i;
+  }
+  __syncthreads();
+  if (t < cb.n) counts[t] = cnt[t];
+}
+
+}  // namespace
+
+hipError_t launch_ef_classes(const int32_t* kq, const int32_t* efq, int64_t nq, int k_all, int ef_all,
+                             const ClassBounds& cb, int32_t* counts, int32_t* lists, hipStream_t s) {
+  hipLaunchKernelGGL(k_ef_classes, dim3(1), dim3(1024), 0, s, kq, efq, nq, k_all, ef_all, cb, counts, lists);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------- estimate test kernel

@@ -108,3 +108,31 @@ def test_exact_duplicates_match_oracle(api):
     G, st = api.finger_build_graph(_t(data), knn_k=6, max_degree=8, entry=0)
     O, ost = og.build(data, 6, 8, 0)
     _compare(G.cpu().numpy(), st, O, ost, "exact duplicates 1200 x 8", exact=True)
+
+
+def test_grouped_build_equals_full_build_on_separated_clusters():
+    """finger_build_graph_grouped with the mixture's components as groups
+    (points sorted by component) returns the graph of the full exact build
+    when every point's nearest neighbours lie in its own component: the
+    96-d, sigma 0.5 mixture of the batching workload at 100,000 points."""
+    import torch
+    from paper_2206_11408_amd import api
+    from workloads import SPECS, make_points
+    print("grouped graph build vs full build (96-d mixture, 100k points)", flush=True)
+    spec = SPECS["c4"].scaled(n=100_000, n_centers=100, nq=1)
+    data, _, lab = make_points(spec, labels=True)
+    order = np.argsort(lab, kind="stable")
+    data = np.ascontiguousarray(data[order])
+    offs = np.concatenate([[0], np.cumsum(np.bincount(lab, minlength=spec.n_centers))])
+    d = torch.as_tensor(data, device="cuda")
+    Gf, sf = api.finger_build_graph(d, knn_k=16, max_degree=32, entry=0)
+    Gg, sg = api.finger_build_graph_grouped(d, offs, knn_k=16, max_degree=32, entry=0)
+    np.testing.assert_array_equal(Gf.cpu().numpy(), Gg.cpu().numpy())
+    for key in ("sym_edges", "sym_degree_max", "components_before_repair", "edges_added"):
+        assert sf[key] == sg[key], key
+    print(f"identical graphs; {sg['components_before_repair']} components, knn {sg['ms_knn']:.1f} ms "
+          f"grouped vs {sf['ms_knn']:.1f} ms full", flush=True)
+    # a group smaller than knn_k + 1 is refused
+    from paper_2206_11408_amd import _lib as L
+    with pytest.raises(L.FingerError):
+        api.finger_build_graph_grouped(d, [0, 10, spec.n], knn_k=16, max_degree=32, entry=0)

@@ -73,8 +73,10 @@ SPECS = {
 
 
 def _draw(rng: np.random.Generator, spec: WorkloadSpec, centers: np.ndarray,
-          count: int, mix: np.ndarray | None = None) -> np.ndarray:
+          count: int, mix: np.ndarray | None = None, labels_out: list | None = None) -> np.ndarray:
     labels = rng.integers(0, spec.n_centers, size=count)
+    if labels_out is not None:
+        labels_out.append(labels)
     m = spec.m
     out = np.empty((count, m), dtype=np.float32)
     step = 1 << 16
@@ -127,8 +129,9 @@ def noise_mix(spec: WorkloadSpec, rng: np.random.Generator) -> np.ndarray:
     return (Q * s) @ Q.T
 
 
-def make_points(spec: WorkloadSpec) -> tuple[np.ndarray, np.ndarray]:
-    """Return (data [n, m], queries [nq, m]) as C-contiguous float32."""
+def make_points(spec: WorkloadSpec, labels: bool = False):
+    """Return (data [n, m], queries [nq, m]) as C-contiguous float32, and with
+    ``labels`` also the mixture component of every data point (int64 [n])."""
     rng = np.random.default_rng(spec.seed)
     if spec.kind == "gauss" or spec.kind == "heavy":
         centers = rng.standard_normal(size=(spec.n_centers, spec.m))
@@ -139,6 +142,9 @@ def make_points(spec: WorkloadSpec) -> tuple[np.ndarray, np.ndarray]:
     else:
         raise ValueError(f"unknown kind {spec.kind}")
     mix = noise_mix(spec, rng) if spec.decay > 0 else None
-    data = _draw(rng, spec, centers, spec.n, mix)
+    lab: list = []
+    data = _draw(rng, spec, centers, spec.n, mix, lab)
     queries = _draw(rng, spec, centers, spec.nq, mix)
+    if labels:
+        return np.ascontiguousarray(data), np.ascontiguousarray(queries), lab[0]
     return np.ascontiguousarray(data), np.ascontiguousarray(queries)
