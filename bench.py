@@ -76,6 +76,137 @@ def measured_traffic(mode_name: str, workload: str):
     return None if ent is None else ent.get("hbm_bytes_per_launch")
 
 
+def c4_leg(a, log, tune_mod) -> dict:
+    """The batching workload (DEEP-10M-96's shape): n points from a mixture
+    of 10,000 Gaussians in 96-d (sigma 0.5), graph = 16-NN symmetrized and
+    pruned to degree 32 with repair, built with each point's kNN taken
+    within its own mixture component (finger_build_graph_grouped; the
+    exactness of that shortcut is measured on a sample), FINGER tables at
+    r = 32 with FP8 edge codes, 16,384 pivot entry points, and 100,000
+    queries with K drawn from {1, 10, 100} and ef from {32, ..., 512}.  One
+    step = query preparation + one search call over all queries: the ef-class
+    partition (one persistent launch per class) against a single launch that
+    reserves LDS for ef_max in every wave, FINGER and plain."""
+    import torch
+    from paper_2206_11408_amd import _lib as L
+    from paper_2206_11408_amd import api
+    from workloads import SPECS, make_points, pick_pivots
+    dev = torch.device("cuda")
+    spec = SPECS["c4"]
+    if a.c4_n != spec.n:
+        spec = spec.scaled(n=a.c4_n, n_centers=max(10, spec.n_centers * a.c4_n // spec.n))
+    t0 = time.time()
+    data, queries, lab = make_points(spec, labels=True)
+    order = np.argsort(lab, kind="stable")
+    data = np.ascontiguousarray(data[order])
+    offs = np.concatenate([[0], np.cumsum(np.bincount(lab, minlength=spec.n_centers))]).astype(np.int64)
+    del lab, order
+    log(f"c4: {spec.n} x {spec.m} points (sorted by component) and {spec.nq} queries in {time.time() - t0:.1f}s")
+    d_data = torch.as_tensor(data, device=dev)
+    d_q = torch.as_tensor(queries, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    dG, gst = api.finger_build_graph_grouped(d_data, offs, knn_k=spec.knn_k, max_degree=spec.max_degree,
+                                             entry=0)
+    torch.cuda.synchronize()
+    graph_s = time.time() - t0
+    log(f"c4: grouped graph in {graph_s:.1f}s: {gst}")
+    # the grouped kNN is the exact kNN for a point whose knn_k + 1 nearest
+    # (itself included) all lie in its own component: checked on a sample
+    rng = np.random.default_rng(11)
+    samp = np.sort(rng.choice(spec.n, 2000, replace=False))
+    si, _ = api.finger_exact_knn(d_data, d_data[torch.as_tensor(samp, device=dev)], spec.knn_k + 1)
+    comp = np.searchsorted(offs, np.arange(spec.n), side="right") - 1
+    si = si.cpu().numpy()
+    grouped_exact = float(np.mean([(comp[si[i]] == comp[samp[i]]).all() for i in range(samp.size)]))
+    log(f"c4: sampled points whose exact {spec.knn_k}-NN lie in their own component: {grouped_exact:.4f}")
+    t0 = time.time()
+    piv = pick_pivots(spec.n, 16384, spec.seed)
+    tab = api.finger_build_tables(d_data, dG, rank=32, code_type=L.CODE_FP8E4M3, pivots=piv, seed=0)
+    torch.cuda.synchronize()
+    tables_s = time.time() - t0
+    log(f"c4: FINGER tables r=32 fp8 in {tables_s:.1f}s")
+    nq = spec.nq
+    qrng = np.random.default_rng(4)
+    K = qrng.choice([1, 10, 100], size=nq).astype(np.int32)
+    EF = qrng.choice([32, 64, 128, 256, 512], size=nq).astype(np.int32)
+    dK, dEF = torch.as_tensor(K, device=dev), torch.as_tensor(EF, device=dev)
+    t0 = time.time()
+    gi, _ = api.finger_exact_knn(d_data, d_q, 100)
+    gi = gi.cpu().numpy()
+    log(f"c4: exact 100-NN of {nq} queries in {time.time() - t0:.1f}s")
+
+    def recall(ids):
+        return float(np.mean([np.isin(ids[i, :K[i]], gi[i, :K[i]]).sum() / K[i] for i in range(nq)]))
+
+    out = {"workload": (f"c4: n={spec.n} m={spec.m} float32, {spec.n_centers}-component Gaussian mixture "
+                        f"(sigma {spec.sigma}), 16-NN within components sym pruned deg 32, 16384 pivots, "
+                        f"r=32 fp8 codes, nq={nq}, K in {{1,10,100}}, ef in {{32,...,512}} per query"),
+           "graph_s": round(graph_s, 2), "tables_s": round(tables_s, 2),
+           "components_before_repair": gst["components_before_repair"],
+           "grouped_knn_exact_fraction": round(grouped_exact, 4)}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for e in kev:   # create the HIP events (torch records them once) before they are handed over
+        e.record()
+    for name, mode, cls in (("finger_classes", L.MODE_FINGER, 0), ("finger_single_reservation", L.MODE_FINGER, 2),
+                            ("plain_classes", L.MODE_PLAIN, 0)):
+        p = api.search_params(mode=mode, k=100, k_max=100, ef=32, entry=-1, k_per_query=dK,
+                              ef_per_query=dEF, ef_max=512, persistent=1, ef_classes=cls)
+        outb = (torch.empty((nq, 100), dtype=torch.int32, device=dev),
+                torch.empty((nq, 100), dtype=torch.float32, device=dev),
+                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
+        for _ in range(max(1, a.warmup)):
+            api.finger_search(tab, d_q, p, out=outb, check=False)
+        torch.cuda.synchronize()
+        steps = max(3, a.steps // 4)
+        kms = []
+        ev0.record()
+        for _ in range(steps):
+            p.kernel_events[0] = kev[0].cuda_event
+            p.kernel_events[1] = kev[1].cuda_event
+            api.finger_search(tab, d_q, p, out=outb, check=False)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        kms = kev[0].elapsed_time(kev[1])   # the last step's search launches
+        api.check_status(outb[2])
+        ids, ctr = outb[0].cpu().numpy(), outb[2].cpu().numpy()
+        B = algorithmic_bytes(ctr, spec.m, spec.max_degree, 32 if mode else 0, 1, 100, True)
+        out[name] = dict(qps=round(nq / ms * 1e3, 1), ms_per_step=round(ms, 3), search_ms=round(kms, 3),
+                         recall=round(recall(ids), 4), alg_gbs=round(B / (kms * 1e-3) / 1e9, 1),
+                         hbm_frac=round(B / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                         exact=round(float(ctr[:, 1].mean()), 1), screened=round(float(ctr[:, 2].mean()), 1),
+                         skipped=round(float(ctr[:, 3].mean()), 1))
+        log(f"c4 {name}: {out[name]}")
+    out["class_partition_gain"] = round(out["finger_classes"]["qps"] / out["finger_single_reservation"]["qps"], 4)
+    out["finger_vs_plain"] = round(out["finger_classes"]["qps"] / out["plain_classes"]["qps"], 4)
+    if a.cpu_sample > 0:
+        # the float64 oracle (compiled) on a sample of one (K, ef) group
+        from oracle import csearch
+        from oracle.build import build as oracle_build
+        t0 = time.time()
+        G = dG.cpu().numpy()
+        orc = oracle_build(data, G, 32, n_samples=100_000, seed=0)
+        sel = np.nonzero((K == 10) & (EF == 64))[0][: max(64, a.cpu_sample // 8)]
+        from oracle.search import pivot_entries
+        ent = pivot_entries(queries[sel], data, piv)
+        X64 = data.astype(np.float64)
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
+        w0 = time.perf_counter()
+        csearch.search_batch(X64, G, queries[sel].astype(np.float64), ent, 64, 10, mode="finger",
+                             tables=orc, threads=cores)
+        out["cpu_oracle"] = {"qps": round(sel.size / (time.perf_counter() - w0), 2), "cores": cores,
+                             "sample": f"{sel.size} queries with K=10, ef=64, FINGER mode, float64 basis "
+                                       f"(not the fp8 codes)"}
+        del X64
+        log(f"c4 oracle: {out['cpu_oracle']} (setup {time.time() - t0:.1f}s)")
+    tab.close()
+    del d_data, d_q, dG
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +257,9 @@ def main() -> int:
     ap.add_argument("--graph", action=argparse.BooleanOptionalAction, default=False,
                     help="time the step as a replay of a captured HIP graph (kernel times "
                          "still come from the eager launches)")
+    ap.add_argument("--c4", action=argparse.BooleanOptionalAction, default=True,
+                    help="the batching leg: 10M x 96, r=32 fp8, 100k queries with mixed K/ef")
+    ap.add_argument("--c4-n", type=int, default=10_000_000, help="points of the batching leg")
     ap.add_argument("--screen-layout", type=int, default=0, choices=(0, 1, 2),
                     help="FINGER screen: 0 library default, 1 coalesced, 2 per-lane chunks")
     ap.add_argument("--copy-probe", action="store_true",
@@ -714,6 +848,8 @@ def main() -> int:
         line["sift_like_spectrum"] = sift
     if wide:
         line["wide_960"] = wide
+    if a.c4:
+        line["batching_c4"] = c4_leg(a, log, tune)
     if a.oracle_legs:
         # graph construction at a size the float64 oracle finishes: the first
         # 20,000 points, same recipe, GPU and oracle side by side

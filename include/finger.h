@@ -236,8 +236,9 @@ typedef struct finger_search_params {
   int32_t persistent;    /* 1: one launch drains an atomic queue of queries
                             (uneven K/ef); 0: static assignment */
   int32_t waves_per_cu;  /* resident query waves per CU; 0 = library default */
-  int32_t visited_capacity; /* visited-set slots per query (power of two,
-                               >= 256); 0 = default from ef_max */
+  int32_t visited_capacity; /* visited-set slots per query in LDS (power of
+                               two, >= 256); ids beyond it go to the spill
+                               table; 0 = default 2048 */
   int32_t spill_capacity; /* visited-set spill slots per resident query wave
                              in the workspace (power of two, >= 64); 0 =
                              default next_pow2(ef_max * max_degree) clamped
@@ -245,9 +246,10 @@ typedef struct finger_search_params {
                              it bounds |V| per query (status bit 0). */
   int32_t code_prefetch; /* FINGER mode: 1 = request every slot's edge code
                             together with the adjacency row (one round trip
-                            fewer, more bytes); -1 = request codes of
-                            unvisited neighbours only; 0 = library default
-                            (prefetch for BF16/FP8 codes) */
+                            fewer; also reads the codes of visited and
+                            padding slots); -1 or 0 (default) = request the
+                            codes of unvisited neighbours only, after the
+                            visited test */
   int32_t ef_classes;    /* with k_per_query or ef_per_query: 0 (default) or 1
                             = partition the queries by ef class (ef_eff =
                             max(ef, K) in (16, 32], (32, 64], ... up to

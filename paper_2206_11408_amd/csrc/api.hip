@@ -395,7 +395,11 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   }
   if (ef_max > kMaxEf) return fail(FINGER_EOVERFLOW, "ef_max = %d exceeds %d", ef_max, kMaxEf);
   if (p->ef_classes < 0 || p->ef_classes > 2) return fail(FINGER_EINVAL, "ef_classes = %d must be 0, 1 or 2", p->ef_classes);
-  auto vis_default = [](int ef) { return std::min(8192, std::max(1024, next_pow2(24 * ef))); };
+  // visited-set slots in LDS: 2048 (8 KB) for every ef.  A query visits about
+  // as many nodes as it computes distances for, and measured on the 1M- and
+  // 10M-point workloads up to ef = 512 a 2048-slot table (spilling to the
+  // global table beyond) beats larger ones, which cost resident waves
+  auto vis_default = [](int) { return 2048; };
   int vis_cap = p->visited_capacity;
   if (vis_cap == 0) vis_cap = vis_default(ef_max);
   if (p->code_prefetch < -1 || p->code_prefetch > 1)
@@ -547,7 +551,7 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.vis_cap = pl.vis_cap;
   L.waves = pl.waves;
   L.persistent = p->persistent;
-  L.prefetch = p->code_prefetch > 0 || (p->code_prefetch == 0 && t->code_type != FINGER_CODE_F32);
+  L.prefetch = p->code_prefetch > 0;
   L.coalesced = p->screen_layout != 2;
   L.log_x = p->log_features;
   L.log_y = p->log_targets;

@@ -31,9 +31,8 @@ def _key(tables: api.Tables, mode: int, ef_max: int, mixed: bool) -> str:
 
 def candidates(mode: int, ef_max: int = 64):
     # visited-set capacity trades LDS per wave (resident waves) against probe
-    # length; the default is next_pow2(24 ef_max) clamped to [1024, 8192]
-    vis_default = min(8192, max(1024, 1 << (24 * ef_max - 1).bit_length()))
-    vis = sorted({vis_default, max(512, vis_default // 2)})
+    # length and spills; the library default is 2048
+    vis = (1024, 2048, 4096)
     out = []
     for wpc in (8, 12, 16, 20, 24, 32):
         for persistent in (0, 1):
