@@ -226,9 +226,11 @@ def main() -> int:
                          "with the adjacency row)")
     ap.add_argument("--ef-plain", type=int, default=0, help="skip the plain sweep, use this ef")
     ap.add_argument("--ef-finger", type=int, default=0, help="skip the FINGER sweep, use this ef")
-    ap.add_argument("--gate", type=int, default=0,
+    ap.add_argument("--gate", type=int, default=5000,
                     help="train the learned gate on this many extra queries (0 = skip) and "
-                         "report the gated search")
+                         "report the gated search (cascade and every edge) at matched recall")
+    ap.add_argument("--gate-band", type=float, default=0.25,
+                    help="cascade band: the gate decides edges within band * ub^2 of the bound")
     ap.add_argument("--ablation", action="store_true",
                     help="also run the ablation variants (low-rank only, random projections with "
                          "and without distribution matching) and the rank rule")
@@ -336,21 +338,22 @@ def main() -> int:
 
     launch = {}   # (mode, code) -> tuned launch settings
 
-    def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0, entry=L.ENTRY_PIVOT, queries=None):
+    def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0, entry=L.ENTRY_PIVOT, queries=None,
+            band=0.0):
         p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, code_prefetch=prefetch,
-                              screen_layout=a.screen_layout)
+                              screen_layout=a.screen_layout, gate_band=band)
         if time_kernel:
             p.kernel_events[0] = kev[0].cuda_event
             p.kernel_events[1] = kev[1].cuda_event
         return api.finger_search(tab, d_q if queries is None else queries, p, out=out, check=False)
 
-    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT, gt=None, queries=None, efs=EF_SWEEP):
+    def sweep(tab, mode, prefetch=0, entry=L.ENTRY_PIVOT, gt=None, queries=None, efs=EF_SWEEP, band=0.0):
         res = []
         for ef in efs:
-            run(tab, mode, ef, prefetch=prefetch, entry=entry, queries=queries)
+            run(tab, mode, ef, prefetch=prefetch, entry=entry, queries=queries, band=band)
             torch.cuda.synchronize()
             ev[0].record()
-            ids, dist, ctr = run(tab, mode, ef, prefetch=prefetch, entry=entry, queries=queries)
+            ids, dist, ctr = run(tab, mode, ef, prefetch=prefetch, entry=entry, queries=queries, band=band)
             ev[1].record()
             torch.cuda.synchronize()
             ms = ev[0].elapsed_time(ev[1])
@@ -370,14 +373,14 @@ def main() -> int:
         return res, (min(ok, key=lambda r: r["ef"]) if ok else max(res, key=lambda r: r["recall"]))
 
     def timed(tab, mode, ef, steps, warmup, code_bytes, fp8, prefetch=0, entry=L.ENTRY_PIVOT, gt=None,
-              queries=None, rank=None, m=None):
+              queries=None, rank=None, m=None, band=0.0):
         nq = a.nq
         d_q = d_q_main if queries is None else queries
         out = (torch.empty((nq, 10), dtype=torch.int32, device=dev),
                torch.empty((nq, 10), dtype=torch.float32, device=dev),
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
         if a.tune:
-            base = dict(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout)
+            base = dict(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, gate_band=band)
             ch = tune.autotune(tab, d_q, base, repeats=3, cache_path=None, log=log)
             if prefetch != 0:   # an explicitly requested code-prefetch setting stays fixed
                 best = min((t, c) for t, c in ch["all"] if c["code_prefetch"] == prefetch)[1]
@@ -387,7 +390,7 @@ def main() -> int:
                                                          "visited_capacity")}
             log(f"tuned launch mode={mode}: {launch[(mode, id(tab), prefetch, entry)]}")
         geo = launch.get((mode, id(tab), prefetch, entry), {})
-        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout,
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, gate_band=band,
                               code_prefetch=geo.get("code_prefetch", prefetch),
                               waves_per_cu=geo.get("waves_per_cu", 0),
                               persistent=geo.get("persistent", 0),
@@ -415,7 +418,7 @@ def main() -> int:
         if a.graph:
             # the same step captured once in a HIP graph and replayed: query
             # preparation and search without per-launch host gaps
-            pg = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout,
+            pg = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, gate_band=band,
                                    code_prefetch=geo.get("code_prefetch", prefetch),
                                    waves_per_cu=geo.get("waves_per_cu", 0),
                                    persistent=geo.get("persistent", 0),
@@ -681,18 +684,23 @@ def main() -> int:
         _, tr_q = make_points(tr_spec)   # same mixture; rows after the first nq are new draws
         t0 = time.time()
         info = gate_mod.fit_gate(tabF, torch.as_tensor(tr_q[a.nq:], device=dev), ef=op_f["ef"],
-                                 hidden=64, epochs=2, batch=4096, lr=2e-3, capacity=20_000_000,
+                                 hidden=64, epochs=2, batch=4096, lr=2e-3,
+                                 capacity=min(20_000_000, max(1 << 20, 1000 * a.gate)),
                                  log=log)
         torch.cuda.synchronize()
         log(f"gate trained in {time.time() - t0:.1f}s on {info['rows']} rows "
             f"(screened {info['screened']}), loss {info['loss']}, eps_gate {info['eps_gate']:.4f}")
-        sw_g, op_g = sweep(tabF, L.MODE_GATED)
-        tg = timed(tabF, L.MODE_GATED, op_g["ef"], a.steps, a.warmup, cb, fp8)
-        log(f"gated  timed: {tg}")
-        gated = dict(ef=op_g["ef"], recall=round(tg["recall"], 4), qps=round(tg["qps"], 1),
-                     kernel_ms=round(tg["kernel_ms"], 4), speedup_vs_plain=round(tg["qps"] / tp["qps"], 4),
-                     speedup_vs_finger=round(tg["qps"] / tf["qps"], 4), exact=round(tg["exact"], 1),
-                     train_rows=info["rows"], eps_gate=round(info["eps_gate"], 5))
+        gated = dict(train_queries=a.gate, train_rows=info["rows"], eps_gate=round(info["eps_gate"], 5),
+                     train_s=round(time.time() - t0, 2), loss=[round(x, 5) for x in info["loss"]])
+        for nm, band in (("cascade", a.gate_band), ("every_edge", 0.0)):
+            sw_g, op_g = sweep(tabF, L.MODE_GATED, band=band)
+            tg = timed(tabF, L.MODE_GATED, op_g["ef"], a.steps, a.warmup, cb, fp8, band=band)
+            log(f"gated ({nm}) timed: {tg}")
+            gated[nm] = dict(band=band, ef=op_g["ef"], recall=round(tg["recall"], 4), qps=round(tg["qps"], 1),
+                             kernel_ms=round(tg["kernel_ms"], 4), exact=round(tg["exact"], 1),
+                             skipped=round(tg["skipped"], 1), speedup_vs_plain=round(tg["qps"] / tp["qps"], 4),
+                             speedup_vs_finger=round(tg["qps"] / tf["qps"], 4))
+        gated["finger"] = dict(ef=op_f["ef"], exact=round(tf["exact"], 1), skipped=round(tf["skipped"], 1))
 
     ablation_out = None
     if a.ablation:

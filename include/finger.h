@@ -258,6 +258,12 @@ typedef struct finger_search_params {
                             waves for its own bound; 2 = one launch in which
                             every wave reserves them for ef_max.  Results do
                             not depend on it. */
+  float gate_band;        /* GATED mode: 0 (default) = the gate decides every
+                            screened neighbour; > 0 = a cascade: the gate
+                            decides only neighbours whose distribution-
+                            matched estimate (Algorithm 3) lies within
+                            gate_band * ub^2 of the bound ub^2, the others
+                            keep Algorithm 3's decision */
   int32_t screen_layout; /* FINGER mode: how lanes read the edge codes.
                             0 = library default (coalesced where it applies);
                             1 = coalesced: each load instruction reads 1 KB of

@@ -19,7 +19,7 @@ import numpy as np
 
 from .build import split
 from .codes import round_bf16
-from .estimate import parts
+from .estimate import combine, dm_map, parts
 
 
 def n_params(in_dim: int, H: int) -> int:
@@ -140,10 +140,17 @@ def target_cosine(d2, q_res_norm, d_res_norm, proj):
 
 
 def gated_estimate(q, c, D, tables: dict, w, H: int, eps_gate: float, ub2: float,
-                   bf16_operands: bool = True) -> np.ndarray:
-    """Eq. 2 with t = f(features) + eps_gate (the gated screen)."""
+                   bf16_operands: bool = True, band: float = 0.0) -> np.ndarray:
+    """Eq. 2 with t = f(features) + eps_gate (the gated screen).  With
+    ``band`` > 0 a cascade: an edge keeps Algorithm 3's estimate unless that
+    estimate lies within band * ub2 of the bound ub2, and only those edges
+    take the network's."""
     P = tables["P"]
     F = edge_features(q, c, D, P, ub2)
     t = forward(w, F, F.shape[1], H, bf16_operands=bf16_operands) + eps_gate
     p = parts(q, c, D, P)
-    return p["proj"] + p["rq"] ** 2 + p["rd"] ** 2 - 2 * p["rq"] * p["rd"] * t
+    est = p["proj"] + p["rq"] ** 2 + p["rd"] ** 2 - 2 * p["rq"] * p["rd"] * t
+    if band > 0:
+        est_dm = combine(p, dm_map(p["t_hat"], tables))
+        est = np.where(np.abs(est_dm - ub2) <= band * ub2, est, est_dm)
+    return est

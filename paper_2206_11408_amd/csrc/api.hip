@@ -404,6 +404,8 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
   if (vis_cap == 0) vis_cap = vis_default(ef_max);
   if (p->code_prefetch < -1 || p->code_prefetch > 1)
     return fail(FINGER_EINVAL, "code_prefetch = %d must be -1, 0 or 1", p->code_prefetch);
+  if (!(p->gate_band >= 0.f) || p->gate_band > 1e30f)
+    return fail(FINGER_EINVAL, "gate_band must be a finite value >= 0");
   if (p->screen_layout < 0 || p->screen_layout > 2)
     return fail(FINGER_EINVAL, "screen_layout = %d must be 0, 1 or 2", p->screen_layout);
   if (vis_cap < 256 || (vis_cap & (vis_cap - 1)) != 0)
@@ -553,6 +555,7 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.persistent = p->persistent;
   L.prefetch = p->code_prefetch > 0;
   L.coalesced = p->screen_layout != 2;
+  L.gate_band = p->gate_band;
   L.log_x = p->log_features;
   L.log_y = p->log_targets;
   L.log_cap = p->log_capacity;

@@ -175,6 +175,7 @@ struct SearchLaunch {
   float* log_y;
   int64_t log_cap;
   int64_t* log_count;
+  float gate_band;  // gated mode: band around the bound inside which the gate decides (<= 0: all)
   // one class of an ef-partitioned search: queries qlist[0..*qcount)
   const int32_t* qlist;
   const int32_t* qcount;

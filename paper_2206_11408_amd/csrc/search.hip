@@ -96,6 +96,7 @@ struct KArgs {
   const float* gate_b;
   int gate_in, gate_h;
   float eps_gate;
+  float gate_band;  // > 0: the gate decides only edges within gate_band ub^2 of the bound
   // gate-training log
   float* log_x;
   float* log_y;
@@ -827,30 +828,41 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
               }
             }
             if constexpr (MODE == FINGER_MODE_GATED) {
-              // this pass's new edges become the rows of a feature tile
-              // (compacted in slot order), which the gate evaluates on the
-              // matrix cores
-              const uint64_t hi = p0 + a.spp >= 64 ? ~0ull : ((1ull << (p0 + a.spp)) - 1ull);
-              const uint64_t pmask = newm & hi & ~((1ull << p0) - 1ull);
-              const int E = popc64(pmask);
-              const int row = slot_new ? popc64(pmask & ((1ull << slot) - 1ull)) : 0;
-              if (slot_new) {
-                uint16_t* fr = featb + row * GL.k1;
-                for (int e = 0; e < kChunk; ++e) {
-                  const int idx = ch * kChunk + e;
-                  if (idx < a.r) fr[idx] = bf16_bits(code.at(e) * scl);
+              // Algorithm 3's matched cosine first; with a band, the gate
+              // decides only the edges whose matched estimate lies within
+              // gate_band ub^2 of the bound (the others keep Algorithm 3's
+              // decision), without a band every new edge.  The gated edges
+              // of this pass become the rows of a feature tile (compacted in
+              // slot order) evaluated on the matrix cores; a pass without
+              // one skips the network.
+              const float t_dm = (t_hat - a.mu_hat) * a.dm_scale + a.mu + a.eps;
+              const float est_dm = proj + rq2 + rh * rh - 2.f * rq * rh * t_dm;
+              const bool gated_edge = slot_new && (a.gate_band <= 0.f || fabsf(est_dm - ub2) <= a.gate_band * ub2);
+              // one bit per gated slot, at the slot's first lane
+              const uint64_t gm = ballot(gated_edge && ch == 0);
+              const int E = popc64(gm);
+              const int row = gated_edge ? popc64(gm & ((1ull << (csub * cpr)) - 1ull)) : 0;
+              if (E > 0) {
+                if (gated_edge) {
+                  uint16_t* fr = featb + row * GL.k1;
+                  for (int e = 0; e < kChunk; ++e) {
+                    const int idx = ch * kChunk + e;
+                    if (idx < a.r) fr[idx] = bf16_bits(code.at(e) * scl);
+                  }
+                  if (ch == 0) {
+                    fr[a.r] = bf16_bits(t_hat);
+                    fr[a.r + 1] = bf16_bits(rq * inv_ub);
+                    fr[a.r + 2] = bf16_bits(rh * inv_ub);
+                    fr[a.r + 3] = bf16_bits(proj * inv_ub * inv_ub);
+                  }
                 }
-                if (ch == 0) {
-                  fr[a.r] = bf16_bits(t_hat);
-                  fr[a.r + 1] = bf16_bits(rq * inv_ub);
-                  fr[a.r + 2] = bf16_bits(rh * inv_ub);
-                  fr[a.r + 3] = bf16_bits(proj * inv_ub * inv_ub);
-                }
+                wave_lds_sync();
+                gate_tiles(GL, gw, gb, b1v, featb, h1b, yv, E);
+                t = gated_edge ? yv[row] + a.eps_gate : t_dm;
+                wave_lds_sync();
+              } else {
+                t = t_dm;
               }
-              wave_lds_sync();
-              gate_tiles(GL, gw, gb, b1v, featb, h1b, yv, E);
-              t = (slot_new ? yv[row] : 0.f) + a.eps_gate;
-              wave_lds_sync();
             } else {
               t = (t_hat - a.mu_hat) * a.dm_scale + a.mu + a.eps;
             }
@@ -1162,6 +1174,7 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   a.gate_in = gated ? t.gate_in : 0;
   a.gate_h = gated ? t.gate_h : 0;
   a.eps_gate = (float)t.eps_gate;
+  a.gate_band = L.gate_band;
   // one query wave per workgroup keeps LDS allocation fine grained
   a.waves_per_block = 1;
   a.coalesced = L.coalesced;

@@ -319,8 +319,9 @@ def test_feature_log_matches_oracle_screening(api):
         assert np.all(np.abs(t.cpu().numpy()) <= 1.0 + 1e-3)
 
 
-def test_gated_search_matches_oracle(api):
-    _say("gated search with seeded gate weights vs the oracle's gated search")
+@pytest.mark.parametrize("band", [0.0, 0.25])
+def test_gated_search_matches_oracle(api, band):
+    _say(f"gated search (band {band}) with seeded gate weights vs the oracle's gated search")
     from workloads import gate_weights
     data, qs, G, _, piv = helpers.c2_small()
     tab = api.finger_build_tables(_t(data), _t(G), rank=64, pivots=piv, seed=0)
@@ -328,31 +329,47 @@ def test_gated_search_matches_oracle(api):
     H, eps_gate, ef = 64, 0.02, 32
     w = gate_weights(2 * 64 + 4, H, seed=5)
     api.finger_gate_attach(tab, w, 2 * 64 + 4, H, eps_gate)
-    gi, gd, gc = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), mode=2, k=10, ef=ef, entry=-1))
+    gi, gd, gc = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), mode=2, k=10, ef=ef, entry=-1,
+                                                             gate_band=band))
     ent = pivot_entries(qs, data, piv)
     w64 = w.astype(np.float64)
 
     def est(q, cur, nbrs, ub2):
-        return gated_estimate(q, data[cur], data[nbrs], orc, w64, H, eps_gate, ub2)
+        return gated_estimate(q, data[cur], data[nbrs], orc, w64, H, eps_gate, ub2, band=band)
 
     sub = np.arange(0, qs.shape[0], 2)
     oi, od, oc, margin = search_batch(data, G, qs[sub], ent[sub], ef, 10, mode="finger",
                                       tables=orc, estimator=est)
     # features are rounded to bf16 on both sides; float32 vs float64 inputs
     # can land on different sides of a rounding boundary, a relative effect
-    # on the estimate far below 1e-4
+    # on the estimate far below 1e-4.  With a band, an edge whose matched
+    # estimate sits within float32 rounding of the band's edge may take the
+    # other estimate on the other side, so that comparison allows a few
+    # differing queries.
     safe = margin > 1e-4
     same = (gi[sub] == oi).all(1)
     _say(f"gated vs oracle: {safe.mean():.2f} of queries with margin > 1e-4, identical on "
          f"{same[safe].mean() if safe.any() else float('nan'):.3f} of them, {same.mean():.3f} overall; "
          f"skip rate {gc[:, 3].sum() / max(gc[:, 2].sum(), 1):.3f}")
-    assert same.mean() >= 0.99
-    assert same[safe].all()
-    np.testing.assert_array_equal(gc[sub][safe][:, :6], oc[safe])
+    if band == 0.0:
+        assert same.mean() >= 0.99
+        assert same[safe].all()
+        np.testing.assert_array_equal(gc[sub][safe][:, :6], oc[safe])
+    else:
+        assert same.mean() >= 0.97
+        assert same[safe].mean() >= 0.97
 
 
 def test_gate_training_and_gain(api):
-    _say("train the gate on logged searches (GPU kernels), then gated vs FINGER on held-out queries")
+    """Train the gate on logged searches (GPU kernels), then compare it with
+    plain FINGER on held-out queries at matched recall: for each screen the
+    smallest ef of a sweep that reaches the recall FINGER reaches at ef = 48,
+    and there its exact distances per query and its search time.  What the
+    network gains (or loses) is measured, not pinned; the test fixes that the
+    comparison is made at matched recall and that the cascade, which runs the
+    network only near the bound, costs less time than gating every edge."""
+    _say("train the gate on logged searches, then gated vs FINGER on held-out queries at matched recall")
+    import torch
     from paper_2206_11408_amd import gate
     from workloads import SPECS, make_points
     data, qs, G, _, piv = helpers.c2_small()
@@ -364,19 +381,47 @@ def test_gate_training_and_gain(api):
                          capacity=1 << 20, log=_say)
     _say(f"gate: rows {info['rows']}, loss by epoch {info['loss']}, eps_gate {info['eps_gate']:.4f}")
     assert info["loss"][-1] < info["loss"][0]
-    gt_i, _ = api.finger_exact_knn(_t(data), _t(qs), 10)
-    gt_i = gt_i.cpu().numpy()
+    gt_i, gt_d = api.finger_exact_knn(_t(data), _t(qs), 10)
+    gt_d = gt_d.cpu().numpy()
 
-    def rec(ids):
-        return float(np.mean([np.isin(ids[i], gt_i[i]).mean() for i in range(ids.shape[0])]))
+    def rec(dist):
+        # tie-aware recall@10: a returned distance counts if it is at most the 10th true one
+        return float(np.mean((dist <= gt_d[:, 9:10] * (1 + 1e-6)).sum(1) / 10.0))
 
-    for ef in (24, 48):
-        fi, _, fc = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), mode=1, k=10, ef=ef, entry=-1))
-        gi, _, gc = (x.cpu().numpy() for x in api.finger_search(tab, _t(qs), mode=2, k=10, ef=ef, entry=-1))
-        _say(f"ef={ef}: FINGER recall {rec(fi):.4f} exact/q {fc[:, 1].mean():.1f} "
-             f"skip {fc[:, 3].sum() / max(fc[:, 2].sum(), 1):.3f} | gated recall {rec(gi):.4f} "
-             f"exact/q {gc[:, 1].mean():.1f} skip {gc[:, 3].sum() / max(gc[:, 2].sum(), 1):.3f}")
-        assert (gc[:, 6] == 0).all()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    d_q = _t(qs)
+
+    def run(mode, ef, band=0.0):
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=-1, gate_band=band)
+        api.finger_search(tab, d_q, p)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(5):
+            ids, dist, ctr = api.finger_search(tab, d_q, p, check=False)
+        ev1.record()
+        torch.cuda.synchronize()
+        api.check_status(ctr)
+        c = ctr.cpu().numpy()
+        return rec(dist.cpu().numpy()), float(c[:, 1].mean()), ev0.elapsed_time(ev1) / 5, \
+            float(c[:, 3].sum() / max(c[:, 2].sum(), 1))
+
+    target = run(1, 48)[0]
+    efs = (16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 128, 160, 200)
+    res = {}
+    for name, mode, band in (("finger", 1, 0.0), ("gated_all", 2, 0.0), ("gated_cascade", 2, 0.25)):
+        for ef in efs:
+            r, exact, ms, skip = run(mode, ef, band)
+            if r >= target:
+                res[name] = dict(ef=ef, recall=r, exact=exact, ms=ms, skip=skip)
+                break
+        _say(f"  {name}: {res.get(name)}")
+    assert set(res) == {"finger", "gated_all", "gated_cascade"}, "a screen never reached the recall"
+    for name in ("gated_all", "gated_cascade"):
+        _say(f"  {name} vs FINGER at recall >= {target:.4f}: exact distances x"
+             f"{res[name]['exact'] / res['finger']['exact']:.3f}, time x{res[name]['ms'] / res['finger']['ms']:.3f}")
+    # the cascade evaluates the network on a subset of the edges at its own
+    # operating point; gating every edge runs it on all of them
+    assert res["gated_cascade"]["ms"] < res["gated_all"]["ms"]
 
 
 # ---------------------------------------------------------------- angular
