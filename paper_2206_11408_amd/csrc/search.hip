@@ -3,31 +3,35 @@
 // form of Supplementary G), one wavefront per query.
 //
 // Per-wave state lives in LDS:
-//   T      the best ef_eff keys (d2, id) found so far, sorted, double
-//          buffered; bit 31 of an id marks "expanded".  The unexpanded
-//          entries of T play the role of the candidate queue C.
+//   T      the best ef_eff keys (d2, id) found so far, sorted; bit 31 of an
+//          id marks "expanded".  The unexpanded entries of T play the role
+//          of the candidate queue C.  Every entry below a running index
+//          (hint) is expanded, so the search for the next centre starts
+//          there.
 //   V      the visited set: open addressing with linear probing; a probe
 //          run longer than kLdsProbes continues in a per-wave table in the
-//          workspace, so the set stays exact.
+//          workspace; when both are full the query reports an overflow.
 //   w      P q_res for the current centre (screening only).
-//   scratch compacted neighbour ids / distances / admitted keys / flags.
+//   scratch compacted neighbour ids / flags, the query and P q.
 //
 // One expansion:
-//   1. pick the best unexpanded entry c of T;
-//   2. one round trip brings c's adjacency row (one id per lane), and when
-//      screening: c.c, P c, alpha_d and rho_d of every slot, and (prefetch
-//      variant) every slot's edge code;
+//   1. pick the best unexpanded entry c of T (and its runner-up);
+//   2. one round trip brings c's adjacency row (one id per lane; already in
+//      registers when c was the previous expansion's runner-up and
+//      speculation is on), and when screening: c.c, P c, alpha_d and rho_d
+//      of every slot, and (prefetch variant) every slot's edge code;
 //   3. test-and-set V for the neighbours;
 //   4. screening: w = Pq - alpha_q P c, then per new slot
-//      t_hat = w.u_d / |w| (code chunks of 32 elements, one per lane, w
-//      read from LDS), the distribution-matching map and Eq. 2; a slot is
-//      skipped iff its estimate exceeds ub = worst d2 of T at the start of
-//      the expansion (the non-prefetch variant loads codes of new slots only,
-//      after step 3);
+//      t_hat = w.u_d / |w|, the distribution-matching map and Eq. 2; a slot
+//      is skipped iff its estimate exceeds ub = worst d2 of T at the start of
+//      the expansion (the non-prefetch variants load codes of new slots
+//      only, after step 3).  The coalesced layout reads 1 KB of the centre's
+//      code block per load instruction; the per-lane layout gives each lane
+//      32 consecutive elements of one slot's code;
 //   5. gather the survivors' vectors (G lanes per vector, float4 loads) and
 //      reduce (q - x)^2 across the group;
-//   6. merge admitted keys into T by rank (ballots over T, broadcast reads of
-//      the few new keys), no sort.
+//   6. merge admitted keys into T in place by rank (ballots over T,
+//      broadcast reads of the few new keys), no sort.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -89,6 +93,7 @@ struct KArgs {
   int vis_cap;
   int waves_per_block;
   int coalesced;  // FINGER mode: use the coalesced screen where it applies
+  int speculate;  // request the runner-up's adjacency row during each expansion
   int lds_wave_bytes;
   int lds_shared_bytes;
   // gate (weights transposed: W1T [in][H], W2T [H][H], W3 [H]; biases float)
@@ -338,6 +343,39 @@ __device__ __forceinline__ float exact_dists(const KArgs& a, const float4* qv, c
   const int lg = l & (G - 1);
   const int slot = l / G;
   float mine = 0.f;
+  if (a.m4 == G * T4 && !a.ip) {
+    // the lanes' pieces cover the vector exactly (m = 512 G T4 / 128): no
+    // range tests.  Slots past cnt load the first id's vector again (lines
+    // the same instruction already requests) instead of branching; their
+    // sums are never handed out.
+    for (int p0 = 0; p0 < cnt; p0 += NP * NPP) {
+      float4 xv[NP][T4];
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        const int ph = p0 + h * NPP + slot;
+        const int id = ids_lds[ph < cnt ? ph : 0];
+        const float4* x4 = reinterpret_cast<const float4*>(a.data + (int64_t)id * a.m) + lg;
+#pragma unroll
+        for (int t = 0; t < T4; ++t) xv[h][t] = x4[G * t];
+      }
+#pragma unroll
+      for (int h = 0; h < NP; ++h) {
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < T4; ++t) {
+          const float4 q = qlds != nullptr ? qlds[lg + G * t] : qv[t];
+          const float dx = q.x - xv[h][t].x, dy = q.y - xv[h][t].y;
+          const float dz = q.z - xv[h][t].z, dw = q.w - xv[h][t].w;
+          acc += dx * dx + dy * dy + dz * dz + dw * dw;
+        }
+        acc = group_sum<G>(acc);
+        const int want = l - p0 - h * NPP;
+        const float got = __shfl(acc, (want >= 0 && want < NPP ? want : 0) * G, 64);
+        if (want >= 0 && want < NPP) mine = got;
+      }
+    }
+    return mine;
+  }
   for (int p0 = 0; p0 < cnt; p0 += NP * NPP) {
     float4 xv[NP][T4];
     int p[NP];
@@ -485,14 +523,13 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   // address arithmetic that depends only on them runs on the scalar unit
   const int wib = uniform_i(threadIdx.x / 64);
   char* base = smem + a.lds_shared_bytes + wib * a.lds_wave_bytes;
-  float* tD[2];
-  int* tI[2];
-  tD[0] = reinterpret_cast<float*>(base);
-  tI[0] = reinterpret_cast<int*>(base + 4 * a.ef_max);
-  tD[1] = reinterpret_cast<float*>(base + 8 * a.ef_max);
-  tI[1] = reinterpret_cast<int*>(base + 12 * a.ef_max);
-  int* vis = reinterpret_cast<int*>(base + 16 * a.ef_max);
-  int* cid = reinterpret_cast<int*>(base + 16 * a.ef_max + 4 * a.vis_cap);
+  // T: [ef_max] distances, then [ef_max] ids with the expanded bit (merged
+  // in place).  Pointers are formed from the LDS base so that the compiler
+  // keeps them in the LDS address space (ds_read/ds_write, not flat)
+  float* TD = reinterpret_cast<float*>(base);
+  int* TI = reinterpret_cast<int*>(base + 4 * a.ef_max);
+  int* vis = reinterpret_cast<int*>(base + 8 * a.ef_max);
+  int* cid = reinterpret_cast<int*>(base + 8 * a.ef_max + 4 * a.vis_cap);
   int* cflag = reinterpret_cast<int*>(cid + 64);
   float* wv = reinterpret_cast<float*>(cflag + 64);  // [rpad] (screening)
   float* pqv = wv + a.rpad;                          // [rpad] this query's Pq
@@ -543,6 +580,11 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   const int lp = kCoal ? l % (kCoal ? LC : 1) : 0;
   const int lg = kCoal ? l / (kCoal ? LC : 1) : 0;
   const int myslot = (lp >> 1) * kSPI + lg;
+  // speculation (a.speculate): while a node is expanded, the adjacency row
+  // of its runner-up (the best unexpanded entry of T after it) is requested
+  // behind the expansion's own first round trip; when the runner-up is the
+  // next centre (no admitted neighbour beats it) that expansion starts with
+  // its row in registers and skips the adjacency round trip.
 
   const int64_t nq_here = a.qcount != nullptr ? (int64_t)uniform_i(*a.qcount) : a.nq;
   for (int64_t it = 0;; ++it) {
@@ -590,31 +632,38 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
     }
     wave_lds_sync();
     const float d_entry = exact_dists<G, T4, 1>(a, qv, qlds, cid, 1);
-    int cur_buf = 0;
     if (l == 0) {
-      tD[0][0] = d_entry;
-      tI[0][0] = entry;
+      TD[0] = d_entry;
+      TI[0] = entry;
     }
     wave_lds_sync();
     int tn = 1;
     int n_exp = 0, n_exact = 1, n_scr = 0, n_skip = 0, n_vis = 1, n_prep = 0;
+    int sid = -1;  // the node whose row snb holds (wave-uniform); -1 = none
+    int snb = -1;  // its adjacency row, one id per lane
+    int hint = 0;  // every entry of T below this index is expanded
 
     while (true) {
-      float* TD = tD[cur_buf];
-      int* TI = tI[cur_buf];
-      // 1. the best unexpanded entry of T
-      int j = -1;
-      for (int b0 = 0; b0 < tn; b0 += 64) {
+      // 1. the best unexpanded entry of T (and, speculating, the runner-up),
+      // scanning from the block that holds index hint
+      int j = -1, cur = -1, nxt = -1;
+      for (int b0 = hint & ~63; b0 < tn; b0 += 64) {
         const int i = b0 + l;
-        const bool un = i < tn && ((uint32_t)TI[i] & kExpanded) == 0u;
-        const uint64_t bm = ballot(un);
-        if (bm) {
-          j = b0 + __ffsll((unsigned long long)bm) - 1;
-          break;
+        const int raw = i < tn ? TI[i] : (int)kExpanded;
+        uint64_t bm = ballot(((uint32_t)raw & kExpanded) == 0u);
+        if (j < 0 && bm) {
+          const int s0 = __ffsll((unsigned long long)bm) - 1;
+          j = b0 + s0;
+          cur = __builtin_amdgcn_readlane(raw, s0);
+          bm &= bm - 1ull;
+        }
+        if (j >= 0) {
+          if (bm) nxt = __builtin_amdgcn_readlane(raw, __ffsll((unsigned long long)bm) - 1);
+          if (bm || !a.speculate) break;
         }
       }
       if (j < 0) break;
-      const int cur = uniform_i(TI[j]);
+      hint = j + 1;
       const float dcur = uniform_f(TD[j]);
       const float ub2 = uniform_f(TD[tn - 1]);
       wave_lds_sync();
@@ -622,9 +671,12 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       ++n_exp;
 
       const bool screening = (MODE != FINGER_MODE_PLAIN) && n_exp > a.warmup && tn == ef_eff;
-      // 2. one round trip: adjacency (+ screening inputs)
+      // 2. one round trip: adjacency (+ screening inputs); the row is
+      // already here when this node was speculated on
+      const bool hit = cur == sid;
       int nb = -1;
-      if (l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
+      if (hit) nb = snb;
+      else if (l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
       float al = 0.f, rh = 0.f, ccv = 0.f;
       // P c of the centre, element l + 64 t in pcv[t] (rpad <= 256), read in
       // this round trip so that forming w below waits on no memory access
@@ -676,6 +728,12 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           for (int t = 0; t < 4; ++t)
             if (l + 64 * t < a.rpad) pcv[t] = a.pc[(int64_t)cur * a.rpad + l + 64 * t];
         }
+      }
+      // the runner-up's row, requested behind this expansion's own
+      sid = a.speculate ? nxt : -1;
+      if (sid >= 0) {
+        snb = -1;
+        if (l < a.deg) snb = a.graph[(int64_t)sid * a.deg + l];
       }
       // 3. visited test-and-set
       int isnew = 0;
@@ -944,18 +1002,36 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       const uint64_t am = ballot(adm);
       const int NA = popc64(am);
       if (NA == 0) continue;
-      // merge by ranks, with the new keys read across lanes: T entry i moves
-      // right by the number of new keys below it; a new key lands at (new
-      // keys below it) + (T keys below it)
-      float* ND = tD[cur_buf ^ 1];
-      int* NI = tI[cur_buf ^ 1];
+      // merge in place, by ranks, with the new keys read across lanes: T
+      // entry i moves right by the number of new keys below it; a new key
+      // lands at (new keys below it) + (T keys below it).  Blocks of 64
+      // entries go from the last one down, so that every entry is read
+      // before anything lands on it (entries only move right); the blocks
+      // wholly below the smallest new key keep their places untouched.
       int my_pos = 0;
-      for (int b0 = 0; b0 < tn; b0 += 64) {
+      uint64_t kmin = ~0ull;
+      int kmin_src = 0;
+      for (uint64_t mm = am; mm; mm &= mm - 1ull) {
+        const int src = __ffsll((unsigned long long)mm) - 1;
+        const uint64_t kj = readlane_u64(key, src);
+        my_pos += kj < key ? 1 : 0;
+        if (kj < kmin) {
+          kmin = kj;
+          kmin_src = src;
+        }
+      }
+      for (int b0 = (tn - 1) & ~63; b0 >= 0; b0 -= 64) {
         const int i = b0 + l;
         const bool valid = i < tn;
         const int raw = valid ? TI[i] : 0;
         const float d = valid ? TD[i] : 0.f;
         const uint64_t tk = valid ? make_key(d, (int)((uint32_t)raw & ~kExpanded)) : ~0ull;
+        const int last = min(tn - b0, 64) - 1;
+        if (readlane_u64(tk, last) < kmin) {
+          // this block and those before it lie below every new key
+          my_pos += b0 + last + 1;
+          break;
+        }
         int shift = 0;
         for (uint64_t mm = am; mm; mm &= mm - 1ull) {
           const int src = __ffsll((unsigned long long)mm) - 1;
@@ -963,26 +1039,24 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           shift += kj < tk ? 1 : 0;
           const int below = popc64(ballot(tk < kj));
           if (l == src) my_pos += below;
-          if (b0 == 0) my_pos += kj < key ? 1 : 0;
         }
-        if (valid && i + shift < ef_eff) {
-          ND[i + shift] = d;
-          NI[i + shift] = raw;
+        if (valid && shift > 0 && i + shift < ef_eff) {
+          TD[i + shift] = d;
+          TI[i + shift] = raw;
         }
       }
       if (adm && my_pos < ef_eff) {
-        ND[my_pos] = key_d2(key);
-        NI[my_pos] = key_id(key);
+        TD[my_pos] = key_d2(key);
+        TI[my_pos] = key_id(key);
       }
+      // entries below the smallest new key's place did not move
+      hint = min(hint, __builtin_amdgcn_readlane(my_pos, kmin_src));
       tn = min(tn + NA, ef_eff);
-      cur_buf ^= 1;
       wave_lds_sync();
     }
 
     // output: the first k keys of T
     {
-      const float* TD = tD[cur_buf];
-      const int* TI = tI[cur_buf];
       for (int jx = l; jx < a.k_max; jx += 64) {
         int id = -1;
         float d = __int_as_float(0x7f800000);
@@ -1093,7 +1167,7 @@ hipError_t launch_codes(const KArgs& a, int code, bool pf, int blocks, int lds, 
 
 int wave_bytes(int ef_max, int vis_cap, int r, int m, int gate_in) {
   const int rpad = rpad_of(r);
-  int b = 16 * ef_max + 4 * vis_cap + 64 * 4 * 2 + 8 * rpad + (r > 0 ? 4 * m : 0);
+  int b = 8 * ef_max + 4 * vis_cap + 64 * 4 * 2 + 8 * rpad + (r > 0 ? 4 * m : 0);
   if (gate_in > 0) {
     // edge features [32][k1] and hidden activations [32][k2] in bf16, outputs [32]
     const GateLayout GL = gate_layout(r, 64);
@@ -1178,6 +1252,7 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   // one query wave per workgroup keeps LDS allocation fine grained
   a.waves_per_block = 1;
   a.coalesced = L.coalesced;
+  a.speculate = L.speculate;
   a.lds_shared_bytes = 0;
   a.lds_wave_bytes = wave_bytes(L.ef_max, L.vis_cap, L.mode == FINGER_MODE_PLAIN ? 0 : t.r, t.m,
                                 gated ? a.gate_in : 0);
