@@ -152,8 +152,7 @@ def c4_leg(a, log, tune_mod) -> dict:
     for name, mode, cls in (("finger_classes", L.MODE_FINGER, 0), ("finger_single_reservation", L.MODE_FINGER, 2),
                             ("plain_classes", L.MODE_PLAIN, 0)):
         p = api.search_params(mode=mode, k=100, k_max=100, ef=32, entry=-1, k_per_query=dK,
-                              ef_per_query=dEF, ef_max=512, persistent=1, ef_classes=cls,
-                              speculate=a.speculate)
+                              ef_per_query=dEF, ef_max=512, persistent=1, ef_classes=cls)
         outb = (torch.empty((nq, 100), dtype=torch.int32, device=dev),
                 torch.empty((nq, 100), dtype=torch.float32, device=dev),
                 torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
@@ -265,9 +264,6 @@ def main() -> int:
     ap.add_argument("--c4-n", type=int, default=10_000_000, help="points of the batching leg")
     ap.add_argument("--screen-layout", type=int, default=0, choices=(0, 1, 2),
                     help="FINGER screen: 0 library default, 1 coalesced, 2 per-lane chunks")
-    ap.add_argument("--speculate", type=int, default=0, choices=(-1, 0, 1),
-                    help="request the runner-up's adjacency row during each expansion: 0 library "
-                         "default (on), 1 on, -1 off")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (the reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -345,7 +341,7 @@ def main() -> int:
     def run(tab, mode, ef, out=None, time_kernel=False, prefetch=0, entry=L.ENTRY_PIVOT, queries=None,
             band=0.0):
         p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, code_prefetch=prefetch,
-                              screen_layout=a.screen_layout, speculate=a.speculate, gate_band=band)
+                              screen_layout=a.screen_layout, gate_band=band)
         if time_kernel:
             p.kernel_events[0] = kev[0].cuda_event
             p.kernel_events[1] = kev[1].cuda_event
@@ -384,7 +380,7 @@ def main() -> int:
                torch.empty((nq, 10), dtype=torch.float32, device=dev),
                torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
         if a.tune:
-            base = dict(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, speculate=a.speculate, gate_band=band)
+            base = dict(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, gate_band=band)
             ch = tune.autotune(tab, d_q, base, repeats=3, cache_path=None, log=log)
             if prefetch != 0:   # an explicitly requested code-prefetch setting stays fixed
                 best = min((t, c) for t, c in ch["all"] if c["code_prefetch"] == prefetch)[1]
@@ -394,7 +390,7 @@ def main() -> int:
                                                          "visited_capacity")}
             log(f"tuned launch mode={mode}: {launch[(mode, id(tab), prefetch, entry)]}")
         geo = launch.get((mode, id(tab), prefetch, entry), {})
-        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, speculate=a.speculate, gate_band=band,
+        p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, gate_band=band,
                               code_prefetch=geo.get("code_prefetch", prefetch),
                               waves_per_cu=geo.get("waves_per_cu", 0),
                               persistent=geo.get("persistent", 0),
@@ -422,7 +418,7 @@ def main() -> int:
         if a.graph:
             # the same step captured once in a HIP graph and replayed: query
             # preparation and search without per-launch host gaps
-            pg = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, speculate=a.speculate, gate_band=band,
+            pg = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, gate_band=band,
                                    code_prefetch=geo.get("code_prefetch", prefetch),
                                    waves_per_cu=geo.get("waves_per_cu", 0),
                                    persistent=geo.get("persistent", 0),

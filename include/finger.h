@@ -273,14 +273,6 @@ typedef struct finger_search_params {
                             fall back to 2); 2 = per-lane chunks: a lane holds
                             32 consecutive elements of one slot's code.
                             Results do not depend on it. */
-  int32_t speculate;     /* 0 = library default (on), 1 = on, -1 = off.  While
-                            a node is expanded, request the adjacency row of
-                            its runner-up (the best unexpanded entry of T
-                            after it) behind the expansion's own requests;
-                            when the runner-up is the next centre (no
-                            admitted neighbour beats it) that expansion
-                            starts with its row in registers, one round trip
-                            fewer.  Results do not depend on it. */
   /* Gate-training log (mode FINGER only; NULL = off).  For every screened
    * neighbour the kernel appends one row of FINGER_GATE_FEATURES(r) floats
    * (see finger_gate_attach) to log_features, its exact squared distance

@@ -61,7 +61,7 @@ class SearchParams(C.Structure):
         ("ef_max", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
         ("visited_capacity", C.c_int32), ("spill_capacity", C.c_int32),
         ("code_prefetch", C.c_int32), ("ef_classes", C.c_int32), ("gate_band", C.c_float),
-        ("screen_layout", C.c_int32), ("speculate", C.c_int32),
+        ("screen_layout", C.c_int32),
         ("log_features", C.c_void_p), ("log_targets", C.c_void_p),
         ("log_capacity", C.c_int64), ("log_count", C.c_void_p),
         ("kernel_events", C.c_void_p * 2),

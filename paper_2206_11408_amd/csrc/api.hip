@@ -408,8 +408,6 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
     return fail(FINGER_EINVAL, "gate_band must be a finite value >= 0");
   if (p->screen_layout < 0 || p->screen_layout > 2)
     return fail(FINGER_EINVAL, "screen_layout = %d must be 0, 1 or 2", p->screen_layout);
-  if (p->speculate < -1 || p->speculate > 1)
-    return fail(FINGER_EINVAL, "speculate = %d must be -1, 0 or 1", p->speculate);
   if (vis_cap < 256 || (vis_cap & (vis_cap - 1)) != 0)
     return fail(FINGER_EINVAL, "visited_capacity = %d must be a power of two >= 256", vis_cap);
   const int gate_in = p->mode == FINGER_MODE_GATED ? t->gate_in : 0;
@@ -557,7 +555,6 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.persistent = p->persistent;
   L.prefetch = p->code_prefetch > 0;
   L.coalesced = p->screen_layout != 2;
-  L.speculate = p->speculate >= 0 ? 1 : 0;
   L.gate_band = p->gate_band;
   L.log_x = p->log_features;
   L.log_y = p->log_targets;

@@ -171,7 +171,6 @@ struct SearchLaunch {
   int persistent;
   int prefetch;     // issue every slot's edge code with the adjacency row
   int coalesced;    // FINGER mode: coalesced screen (code rows of 32..256 bytes, degree <= 32)
-  int speculate;    // request the runner-up's adjacency row during each expansion
   float* log_x;
   float* log_y;
   int64_t log_cap;

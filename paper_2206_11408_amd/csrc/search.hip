@@ -15,11 +15,10 @@
 //   scratch compacted neighbour ids / flags, the query and P q.
 //
 // One expansion:
-//   1. pick the best unexpanded entry c of T (and its runner-up);
-//   2. one round trip brings c's adjacency row (one id per lane; already in
-//      registers when c was the previous expansion's runner-up and
-//      speculation is on), and when screening: c.c, P c, alpha_d and rho_d
-//      of every slot, and (prefetch variant) every slot's edge code;
+//   1. pick the best unexpanded entry c of T;
+//   2. one round trip brings c's adjacency row (one id per lane), and when
+//      screening: c.c, P c, alpha_d and rho_d of every slot, and (prefetch
+//      variant) every slot's edge code;
 //   3. test-and-set V for the neighbours;
 //   4. screening: w = Pq - alpha_q P c, then per new slot
 //      t_hat = w.u_d / |w|, the distribution-matching map and Eq. 2; a slot
@@ -93,7 +92,6 @@ struct KArgs {
   int vis_cap;
   int waves_per_block;
   int coalesced;  // FINGER mode: use the coalesced screen where it applies
-  int speculate;  // request the runner-up's adjacency row during each expansion
   int lds_wave_bytes;
   int lds_shared_bytes;
   // gate (weights transposed: W1T [in][H], W2T [H][H], W3 [H]; biases float)
@@ -580,11 +578,6 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   const int lp = kCoal ? l % (kCoal ? LC : 1) : 0;
   const int lg = kCoal ? l / (kCoal ? LC : 1) : 0;
   const int myslot = (lp >> 1) * kSPI + lg;
-  // speculation (a.speculate): while a node is expanded, the adjacency row
-  // of its runner-up (the best unexpanded entry of T after it) is requested
-  // behind the expansion's own first round trip; when the runner-up is the
-  // next centre (no admitted neighbour beats it) that expansion starts with
-  // its row in registers and skips the adjacency round trip.
 
   const int64_t nq_here = a.qcount != nullptr ? (int64_t)uniform_i(*a.qcount) : a.nq;
   for (int64_t it = 0;; ++it) {
@@ -639,27 +632,21 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
     wave_lds_sync();
     int tn = 1;
     int n_exp = 0, n_exact = 1, n_scr = 0, n_skip = 0, n_vis = 1, n_prep = 0;
-    int sid = -1;  // the node whose row snb holds (wave-uniform); -1 = none
-    int snb = -1;  // its adjacency row, one id per lane
     int hint = 0;  // every entry of T below this index is expanded
 
     while (true) {
-      // 1. the best unexpanded entry of T (and, speculating, the runner-up),
-      // scanning from the block that holds index hint
-      int j = -1, cur = -1, nxt = -1;
+      // 1. the best unexpanded entry of T, scanning from the block that
+      // holds index hint
+      int j = -1, cur = -1;
       for (int b0 = hint & ~63; b0 < tn; b0 += 64) {
         const int i = b0 + l;
         const int raw = i < tn ? TI[i] : (int)kExpanded;
-        uint64_t bm = ballot(((uint32_t)raw & kExpanded) == 0u);
-        if (j < 0 && bm) {
+        const uint64_t bm = ballot(((uint32_t)raw & kExpanded) == 0u);
+        if (bm) {
           const int s0 = __ffsll((unsigned long long)bm) - 1;
           j = b0 + s0;
           cur = __builtin_amdgcn_readlane(raw, s0);
-          bm &= bm - 1ull;
-        }
-        if (j >= 0) {
-          if (bm) nxt = __builtin_amdgcn_readlane(raw, __ffsll((unsigned long long)bm) - 1);
-          if (bm || !a.speculate) break;
+          break;
         }
       }
       if (j < 0) break;
@@ -671,12 +658,9 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       ++n_exp;
 
       const bool screening = (MODE != FINGER_MODE_PLAIN) && n_exp > a.warmup && tn == ef_eff;
-      // 2. one round trip: adjacency (+ screening inputs); the row is
-      // already here when this node was speculated on
-      const bool hit = cur == sid;
+      // 2. one round trip: adjacency (+ screening inputs)
       int nb = -1;
-      if (hit) nb = snb;
-      else if (l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
+      if (l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
       float al = 0.f, rh = 0.f, ccv = 0.f;
       // P c of the centre, element l + 64 t in pcv[t] (rpad <= 256), read in
       // this round trip so that forming w below waits on no memory access
@@ -728,12 +712,6 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           for (int t = 0; t < 4; ++t)
             if (l + 64 * t < a.rpad) pcv[t] = a.pc[(int64_t)cur * a.rpad + l + 64 * t];
         }
-      }
-      // the runner-up's row, requested behind this expansion's own
-      sid = a.speculate ? nxt : -1;
-      if (sid >= 0) {
-        snb = -1;
-        if (l < a.deg) snb = a.graph[(int64_t)sid * a.deg + l];
       }
       // 3. visited test-and-set
       int isnew = 0;
@@ -1252,7 +1230,6 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   // one query wave per workgroup keeps LDS allocation fine grained
   a.waves_per_block = 1;
   a.coalesced = L.coalesced;
-  a.speculate = L.speculate;
   a.lds_shared_bytes = 0;
   a.lds_wave_bytes = wave_bytes(L.ef_max, L.vis_cap, L.mode == FINGER_MODE_PLAIN ? 0 : t.r, t.m,
                                 gated ? a.gate_in : 0);

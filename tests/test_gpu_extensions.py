@@ -193,45 +193,6 @@ def test_screen_layouts_agree(api, code, rank):
     tab.close()
 
 
-@pytest.mark.parametrize("mode,code,layout,pf", [(0, 0, 0, 0), (1, 0, 1, -1), (1, 0, 2, -1), (1, 0, 1, 1),
-                                                  (1, 1, 1, -1), (1, 2, 1, -1), (1, 2, 2, 1)])
-def test_speculation_changes_nothing(api, mode, code, layout, pf):
-    """Requesting the runner-up's adjacency row during each expansion only
-    changes when the row arrives: ids, distances and every counter are the
-    same bits with and without it, in both modes, every code format and
-    screen layout, and in a persistent launch with per-query K and ef."""
-    _say(f"speculation on/off: mode {mode}, code {code}, layout {layout}, prefetch {pf}")
-    import torch
-    data, qs, G, _, piv = helpers.c2_small()
-    tab = api.finger_build_tables(_t(data), _t(G), rank=64, pivots=piv, code_type=code)
-    rng = np.random.default_rng(7)
-    K = torch.as_tensor(rng.choice([1, 10, 20], qs.shape[0]).astype(np.int32), device="cuda")
-    EF = torch.as_tensor(rng.choice([16, 48, 96, 160], qs.shape[0]).astype(np.int32), device="cuda")
-    for extra in (dict(k=10, ef=48), dict(k=20, k_max=20, ef=16, ef_max=160, k_per_query=K, ef_per_query=EF,
-                                           persistent=1)):
-        got = {}
-        for spec in (1, -1):
-            p = api.search_params(mode=mode, entry=-1, screen_layout=layout, code_prefetch=pf, speculate=spec,
-                                  **extra)
-            got[spec] = [x.cpu().numpy() for x in api.finger_search(tab, _t(qs), p)]
-        for x, y in zip(got[1], got[-1]):
-            np.testing.assert_array_equal(x, y)
-    tab.close()
-
-
-def test_speculation_changes_nothing_angular_and_ip(api):
-    from paper_2206_11408_amd import _lib as L
-    data, qs, G, entry, _ = helpers.c1()
-    for metric in (L.ANGULAR, L.IP):
-        tab = api.finger_build_tables(_t(data), _t(G), rank=16, metric=metric)
-        for mode in (0, 1):
-            got = {spec: [x.cpu().numpy() for x in api.finger_search(
-                tab, _t(qs), mode=mode, k=10, ef=64, entry=entry, speculate=spec)] for spec in (1, -1)}
-            for x, y in zip(got[1], got[-1]):
-                np.testing.assert_array_equal(x, y)
-        tab.close()
-
-
 def test_autotuner_picks_a_valid_setting(api, tmp_path):
     from paper_2206_11408_amd import tune
     data, qs, G, _, piv = helpers.c2_small()
