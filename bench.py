@@ -149,8 +149,9 @@ def c4_leg(a, log, tune_mod) -> dict:
     kev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     for e in kev:   # create the HIP events (torch records them once) before they are handed over
         e.record()
-    for name, mode, cls in (("finger_classes", L.MODE_FINGER, 0), ("finger_single_reservation", L.MODE_FINGER, 2),
-                            ("plain_classes", L.MODE_PLAIN, 0)):
+    for name, mode, cls in (("finger", L.MODE_FINGER, 0), ("finger_classes", L.MODE_FINGER, 1),
+                            ("finger_single_reservation", L.MODE_FINGER, 2), ("plain", L.MODE_PLAIN, 0),
+                            ("plain_classes", L.MODE_PLAIN, 1)):
         p = api.search_params(mode=mode, k=100, k_max=100, ef=32, entry=-1, k_per_query=dK,
                               ef_per_query=dEF, ef_max=512, persistent=1, ef_classes=cls)
         outb = (torch.empty((nq, 100), dtype=torch.int32, device=dev),
@@ -179,8 +180,11 @@ def c4_leg(a, log, tune_mod) -> dict:
                          exact=round(float(ctr[:, 1].mean()), 1), screened=round(float(ctr[:, 2].mean()), 1),
                          skipped=round(float(ctr[:, 3].mean()), 1))
         log(f"c4 {name}: {out[name]}")
-    out["class_partition_gain"] = round(out["finger_classes"]["qps"] / out["finger_single_reservation"]["qps"], 4)
-    out["finger_vs_plain"] = round(out["finger_classes"]["qps"] / out["plain_classes"]["qps"], 4)
+    # the default (one launch, largest ef class first) against one launch per
+    # class and against one launch serving the queries in index order
+    out["longest_first_vs_classes"] = round(out["finger"]["qps"] / out["finger_classes"]["qps"], 4)
+    out["longest_first_vs_query_order"] = round(out["finger"]["qps"] / out["finger_single_reservation"]["qps"], 4)
+    out["finger_vs_plain"] = round(out["finger"]["qps"] / out["plain"]["qps"], 4)
     if a.cpu_sample > 0:
         # the float64 oracle (compiled) on a sample of one (K, ef) group
         from oracle import csearch

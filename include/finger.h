@@ -250,14 +250,17 @@ typedef struct finger_search_params {
                             padding slots); -1 or 0 (default) = request the
                             codes of unvisited neighbours only, after the
                             visited test */
-  int32_t ef_classes;    /* with k_per_query or ef_per_query: 0 (default) or 1
-                            = partition the queries by ef class (ef_eff =
-                            max(ef, K) in (16, 32], (32, 64], ... up to
-                            ef_max) and run one persistent launch per class,
-                            each reserving LDS, a visited table and resident
-                            waves for its own bound; 2 = one launch in which
-                            every wave reserves them for ef_max.  Results do
-                            not depend on it. */
+  int32_t ef_classes;    /* with k_per_query or ef_per_query, how the queries
+                            are grouped by ef class (ef_eff = max(ef, K) in
+                            (16, 32], (32, 64], ... up to ef_max):
+                            0 (default) or 3 = one persistent launch, every
+                            wave reserving LDS, a visited table and resident
+                            waves for ef_max, its queue serving the largest
+                            class first so that the short queries fill the
+                            launch's end; 1 = one persistent launch per
+                            class, each reserving for its own bound; 2 = one
+                            launch reserving for ef_max with the queue in
+                            query order.  Results do not depend on it. */
   float gate_band;        /* GATED mode: 0 (default) = the gate decides every
                             screened neighbour; > 0 = a cascade: the gate
                             decides only neighbours whose distribution-

@@ -394,7 +394,8 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
     if (ef_max < need) ef_max = need;
   }
   if (ef_max > kMaxEf) return fail(FINGER_EOVERFLOW, "ef_max = %d exceeds %d", ef_max, kMaxEf);
-  if (p->ef_classes < 0 || p->ef_classes > 2) return fail(FINGER_EINVAL, "ef_classes = %d must be 0, 1 or 2", p->ef_classes);
+  if (p->ef_classes < 0 || p->ef_classes > 3)
+    return fail(FINGER_EINVAL, "ef_classes = %d must be 0, 1, 2 or 3", p->ef_classes);
   // visited-set slots in LDS: 2048 (8 KB) for every ef.  A query visits about
   // as many nodes as it computes distances for, and measured on the 1M- and
   // 10M-point workloads up to ef = 512 a 2048-slot table (spilling to the
@@ -568,6 +569,16 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   if (ev0) HIPCHK(hipEventRecord(ev0, s));
   if (pl.cb.n == 0) {
     HIPCHK(launch_search(*t, L, s));
+  } else if (p->ef_classes == 0 || p->ef_classes == 3) {
+    // one persistent launch reserving for ef_max, its queue serving the
+    // largest ef class first (the short queries fill the launch's end)
+    SearchLaunch Lc = L;
+    Lc.persistent = 1;
+    Lc.qlist = lists;
+    Lc.qcount = counts;
+    Lc.nclass = pl.cb.n;
+    Lc.list_stride = nq;
+    HIPCHK(launch_search(*t, Lc, s));
   } else {
     // one persistent launch per ef class, each sized for its own bound
     for (int c = 0; c < pl.cb.n; ++c) {

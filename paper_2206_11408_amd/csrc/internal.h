@@ -176,9 +176,13 @@ struct SearchLaunch {
   int64_t log_cap;
   int64_t* log_count;
   float gate_band;  // gated mode: band around the bound inside which the gate decides (<= 0: all)
-  // one class of an ef-partitioned search: queries qlist[0..*qcount)
+  // one class of an ef-partitioned search: queries qlist[0..*qcount); with
+  // nclass > 0 one launch over nclass class lists (stride list_stride),
+  // the largest class first
   const int32_t* qlist;
   const int32_t* qcount;
+  int nclass;
+  int64_t list_stride;
 };
 hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s);
 

@@ -83,9 +83,14 @@ struct KArgs {
   // scheduling / scratch
   int32_t* queue;
   int persistent;
-  // one ef class of a partitioned launch: the queries are qlist[0..*qcount)
+  // one ef class of a partitioned launch: the queries are qlist[0..*qcount);
+  // with nclass > 0 instead one launch over all classes, qlist holding class
+  // c's queries at qlist + c list_stride and qcount[c] of them, served from
+  // the last (largest) class down
   const int32_t* qlist;
   const int32_t* qcount;
+  int nclass;
+  int64_t list_stride;
   int ip;     // inner-product metric: distance -q.x
   int32_t* spill;
   int spill_slots;
@@ -579,7 +584,13 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   const int lg = kCoal ? l / (kCoal ? LC : 1) : 0;
   const int myslot = (lp >> 1) * kSPI + lg;
 
-  const int64_t nq_here = a.qcount != nullptr ? (int64_t)uniform_i(*a.qcount) : a.nq;
+  int64_t nq_here = a.nq;
+  if (a.nclass > 0) {
+    nq_here = 0;
+    for (int c = 0; c < a.nclass; ++c) nq_here += uniform_i(a.qcount[c]);
+  } else if (a.qcount != nullptr) {
+    nq_here = uniform_i(*a.qcount);
+  }
   for (int64_t it = 0;; ++it) {
     int64_t qi;
     if (a.persistent) {
@@ -590,7 +601,20 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       qi = (int64_t)wave_global + it * total_waves;
     }
     if (qi >= nq_here) break;
-    if (a.qlist != nullptr) qi = uniform_i(a.qlist[qi]);
+    if (a.nclass > 0) {
+      // queue position -> query, the largest ef class first
+      int64_t r = qi;
+      for (int c = a.nclass - 1; c >= 0; --c) {
+        const int64_t cn = uniform_i(a.qcount[c]);
+        if (r < cn) {
+          qi = uniform_i(a.qlist[c * a.list_stride + r]);
+          break;
+        }
+        r -= cn;
+      }
+    } else if (a.qlist != nullptr) {
+      qi = uniform_i(a.qlist[qi]);
+    }
 
     const int k = a.kq ? a.kq[qi] : a.k_all;
     const int ef = a.efq ? a.efq[qi] : a.ef_all;
@@ -1213,6 +1237,8 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   a.persistent = L.persistent;
   a.qlist = L.qlist;
   a.qcount = L.qcount;
+  a.nclass = L.nclass;
+  a.list_stride = L.list_stride;
   a.spill = L.spill;
   a.spill_slots = L.spill_slots_per_wave;
   a.vis_cap = L.vis_cap;

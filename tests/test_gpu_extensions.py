@@ -130,7 +130,8 @@ def test_persistent_mixed_k_ef_equals_separate_launches(api):
 def test_ef_class_partition_matches_single_reservation(api, mode):
     """Queries with per-query K and ef partitioned into ef classes, one
     persistent launch per class sized for its own bound, return exactly what
-    one launch that reserves LDS for ef_max in every wave returns."""
+    one launch that reserves LDS for ef_max in every wave returns, whether
+    that launch serves the queries in index order or the largest class first."""
     _say(f"ef-class partition vs single ef_max reservation, mode={mode}")
     data, qs, G, _, piv = helpers.c2_small()
     tab = api.finger_build_tables(_t(data), _t(G), rank=64 if mode else 0, pivots=piv)
@@ -138,12 +139,13 @@ def test_ef_class_partition_matches_single_reservation(api, mode):
     K = rng.choice([1, 10, 100], size=qs.shape[0]).astype(np.int32)
     EF = rng.choice([16, 32, 64, 128, 256, 512], size=qs.shape[0]).astype(np.int32)
     out = {}
-    for cls in (0, 2):
+    for cls in (0, 1, 2, 3):
         p = api.search_params(mode=mode, k=100, k_max=100, ef=32, entry=-1, k_per_query=_t(K),
                               ef_per_query=_t(EF), ef_max=512, persistent=1, ef_classes=cls)
         out[cls] = [x.cpu().numpy() for x in api.finger_search(tab, _t(qs), p)]
-    for x, y in zip(out[0], out[2]):
-        np.testing.assert_array_equal(x, y)
+    for other in (1, 2, 3):
+        for x, y in zip(out[0], out[other]):
+            np.testing.assert_array_equal(x, y)
     tab.close()
 
 
