@@ -152,8 +152,13 @@ def c4_leg(a, log, tune_mod) -> dict:
     for name, mode, cls in (("finger", L.MODE_FINGER, 0), ("finger_classes", L.MODE_FINGER, 1),
                             ("finger_single_reservation", L.MODE_FINGER, 2), ("plain", L.MODE_PLAIN, 0),
                             ("plain_classes", L.MODE_PLAIN, 1)):
-        p = api.search_params(mode=mode, k=100, k_max=100, ef=32, entry=-1, k_per_query=dK,
-                              ef_per_query=dEF, ef_max=512, persistent=1, ef_classes=cls)
+        base = dict(mode=mode, k=100, k_max=100, ef=32, entry=-1, k_per_query=dK, ef_per_query=dEF,
+                    ef_max=512, persistent=1, ef_classes=cls)
+        geo = {}
+        if a.tune:
+            ch = tune_mod.autotune(tab, d_q, base, repeats=2, cache_path=None)
+            geo = {k: ch[k] for k in ("waves_per_cu", "code_prefetch", "visited_capacity")}
+        p = api.search_params(**{**base, **geo})
         outb = (torch.empty((nq, 100), dtype=torch.int32, device=dev),
                 torch.empty((nq, 100), dtype=torch.float32, device=dev),
                 torch.empty((nq, L.NCOUNTERS), dtype=torch.int32, device=dev))
@@ -178,7 +183,7 @@ def c4_leg(a, log, tune_mod) -> dict:
                          recall=round(recall(ids), 4), alg_gbs=round(B / (kms * 1e-3) / 1e9, 1),
                          hbm_frac=round(B / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                          exact=round(float(ctr[:, 1].mean()), 1), screened=round(float(ctr[:, 2].mean()), 1),
-                         skipped=round(float(ctr[:, 3].mean()), 1))
+                         skipped=round(float(ctr[:, 3].mean()), 1), launch=geo or "library default")
         log(f"c4 {name}: {out[name]}")
     # the default (one launch, largest ef class first) against one launch per
     # class and against one launch serving the queries in index order
@@ -248,8 +253,8 @@ def main() -> int:
                          "decaying noise spectrum calibrated to the paper's SIFT rank")
     ap.add_argument("--spectrum-codes", default="",
                     help="extra FINGER code variants (code[:pf|:nopf]) on the spectrum leg")
-    ap.add_argument("--wide", default="c3s",
-                    help="comma-separated 1M x 960 workloads (c3a: isotropic noise, c3s: decaying "
+    ap.add_argument("--wide", default="c3s,c3b",
+                    help="comma-separated precision workloads: 1M x 960 (c3a: isotropic noise, c3s: decaying "
                          "spectrum) on which to also measure plain and FINGER (bf16 and fp8 codes); "
                          "empty to skip")
     ap.add_argument("--wide-rule-rank", action="store_true",
@@ -597,33 +602,50 @@ def main() -> int:
         del dd2, dq2, dG2
 
     wide = {}
+    angular = {}
     for wname in [w for w in a.wide.split(",") if w]:
         # a 960-d workload (GIST-1M-960's shape): a vector is 3,840 bytes
         # against 136 (bf16) or 72 (fp8) bytes per edge code at r = 64, the
-        # regime where screening can pay in bytes if the residuals are low-rank
+        # regime where screening can pay in bytes if the residuals are low-rank;
+        # c3b (GloVe-1.2M-100's shape): 100-d heavy-tailed vectors under the
+        # angular metric (Supplementary A), every row scaled by a random
+        # factor so that the metric's normalization matters
         spec3 = SPECS[wname].scaled(nq=a.nq)
+        ang = wname == "c3b"
+        metric3 = L.ANGULAR if ang else L.L2
         t0 = time.time()
         data3, q3 = make_points(spec3)
+        if ang:
+            srng = np.random.default_rng(3)
+            data3 = (data3 * srng.uniform(0.5, 4.0, (data3.shape[0], 1))).astype(np.float32)
+            q3 = (q3 * srng.uniform(0.5, 4.0, (q3.shape[0], 1))).astype(np.float32)
         dd3 = torch.as_tensor(data3, device=dev)
         dq3 = torch.as_tensor(q3, device=dev)
         log(f"{wname} points n={spec3.n} m={spec3.m} in {time.time() - t0:.1f}s")
         t0 = time.time()
+        ent3 = medoid(data3 / np.linalg.norm(data3, axis=1, keepdims=True) if ang else data3)
         dG3, gst3 = api.finger_build_graph(dd3, knn_k=spec3.knn_k, max_degree=spec3.max_degree,
-                                           entry=medoid(data3))
+                                           entry=ent3, metric=metric3)
         torch.cuda.synchronize()
         log(f"{wname} graph in {time.time() - t0:.1f}s: {gst3}")
         piv3 = pick_pivots(spec3.n, a.pivots, spec3.seed)
-        gi3, gd3 = api.finger_exact_knn(dd3, dq3, 10)
+        gi3, gd3 = api.finger_exact_knn(dd3, dq3, 10, metric=metric3)
         gt3 = (gi3.cpu().numpy(), gd3.cpu().numpy())
-        noise = f"noise spectrum i^-{spec3.decay}" if spec3.decay > 0 else "isotropic noise"
-        res = {"workload": (f"{wname}: n={spec3.n} m={spec3.m} float32, {spec3.n_centers} uniform centres + "
-                            f"{spec3.sigma} Gaussian {noise}, 16-NN sym pruned deg 32, {a.pivots} pivots, "
-                            f"nq={a.nq}, K=10")}
+        if ang:
+            desc = (f"{wname}: n={spec3.n} m={spec3.m} float32, {spec3.n_centers} N(0,I) centres + Student-t(3) "
+                    f"noise, rows scaled by U(0.5, 4), angular metric, 16-NN sym pruned deg 32, {a.pivots} "
+                    f"pivots, nq={a.nq}, K=10")
+        else:
+            noise = f"noise spectrum i^-{spec3.decay}" if spec3.decay > 0 else "isotropic noise"
+            desc = (f"{wname}: n={spec3.n} m={spec3.m} float32, {spec3.n_centers} uniform centres + "
+                    f"{spec3.sigma} Gaussian {noise}, 16-NN sym pruned deg 32, {a.pivots} pivots, "
+                    f"nq={a.nq}, K=10")
+        res = {"workload": desc}
         efs3 = EF_SWEEP + (256, 320, 400)
         for rank in (a.rank, 16) if a.wide_rule_rank and a.rank != 16 else (a.rank,):
             for code in ("bf16", "fp8"):
                 tw = api.finger_build_tables(dd3, dG3, rank=rank, code_type=code_of[code][0], pivots=piv3,
-                                             seed=0)
+                                             seed=0, metric=metric3)
                 res[f"corr_xy_r{rank}"] = round(tw.info()["corr_xy"], 4)
                 legs = [(f"finger_{code}_r{rank}", L.MODE_FINGER)]
                 if code == "bf16" and rank == a.rank:
@@ -642,7 +664,7 @@ def main() -> int:
                     if mode == L.MODE_FINGER:
                         res[nm]["speedup_vs_plain"] = round(th["qps"] / res["plain"]["qps"], 4)
                 tw.close()
-        wide[wname] = res
+        (angular if ang else wide)[wname] = res
         del dd3, dq3, dG3
         torch.cuda.empty_cache()
 
@@ -860,6 +882,8 @@ def main() -> int:
         line["sift_like_spectrum"] = sift
     if wide:
         line["wide_960"] = wide
+    if angular:
+        line["angular_100"] = angular
     if a.c4:
         line["batching_c4"] = c4_leg(a, log, tune)
     if a.oracle_legs:

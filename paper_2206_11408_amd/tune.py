@@ -29,13 +29,14 @@ def _key(tables: api.Tables, mode: int, ef_max: int, mixed: bool) -> str:
             f"code{inf['code_type']}|mode{mode}|ef{ef_max}|mixed{int(mixed)}")
 
 
-def candidates(mode: int, ef_max: int = 64):
+def candidates(mode: int, ef_max: int = 64, mixed: bool = False):
     # visited-set capacity trades LDS per wave (resident waves) against probe
-    # length and spills; the library default is 2048
+    # length and spills; the library default is 2048.  Searches with per-query
+    # K or ef always run persistent launches.
     vis = (1024, 2048, 4096)
     out = []
     for wpc in (8, 12, 16, 20, 24, 32):
-        for persistent in (0, 1):
+        for persistent in ((1,) if mixed else (0, 1)):
             pfs = (0,) if mode == L.MODE_PLAIN else (-1, 1)
             for pf in pfs:
                 for vc in vis:
@@ -65,7 +66,7 @@ def autotune(tables: api.Tables, queries: torch.Tensor, base: dict, repeats: int
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     timings = []
-    for cand in candidates(mode, ef_max):
+    for cand in candidates(mode, ef_max, mixed):
         p = api.search_params(**{**base, **cand})
         try:
             api.finger_search(tables, queries, p)
