@@ -8,9 +8,10 @@
 //          of the candidate queue C.  Every entry below a running index
 //          (hint) is expanded, so the search for the next centre starts
 //          there.
-//   V      the visited set: open addressing with linear probing; a probe
-//          run longer than kLdsProbes continues in a per-wave table in the
-//          workspace; when both are full the query reports an overflow.
+//   V      the visited set: open addressing with linear probing over
+//          buckets of four slots; a probe run longer than kLdsProbes slots
+//          continues in a per-wave table in the workspace; when both are
+//          full the query reports an overflow.
 //   w      P q_res for the current centre (screening only).
 //   scratch compacted neighbour ids / flags, the query and P q.
 //
@@ -117,16 +118,31 @@ __device__ __forceinline__ uint32_t hash_id(int id) { return (uint32_t)id * 2654
 // Exact membership test-and-insert.  Returns 1 if id was new, 0 if already
 // visited; sets spilled when the global table was touched, overflow when
 // both tables were exhausted (the id is then treated as visited).
+// The LDS table is probed linearly in buckets of four slots: one 16-byte
+// read examines a bucket; an id present there is visited; otherwise the id
+// goes into the bucket's first empty slot (compare-and-swap, the next empty
+// one if another lane took it), and only a full bucket moves the probe on.
+// Slots only ever fill, so an id is always in the first empty slot of its
+// probe sequence or before it; lanes with the same id see the same bucket
+// and race for the same slot, so an id is inserted once.
 __device__ __forceinline__ int visit(int id, int* __restrict__ tab, uint32_t cap_mask,
                                      int* __restrict__ spill, uint32_t spill_mask,
                                      bool& spilled, bool& overflow) {
-  uint32_t h = (hash_id(id) >> 7) & cap_mask;
+  uint32_t h = (hash_id(id) >> 7) & cap_mask & ~3u;
 #pragma unroll 1
-  for (int p = 0; p < kLdsProbes; ++p) {
-    const int old = atomicCAS(&tab[h], -1, id);
-    if (old == -1) return 1;
-    if (old == id) return 0;
-    h = (h + 1) & cap_mask;
+  for (int p = 0; p < kLdsProbes / 4; ++p) {
+    const int4 b = *reinterpret_cast<const int4*>(tab + h);
+    if (b.x == id || b.y == id || b.z == id || b.w == id) return 0;
+    const int v[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (v[e] == -1) {
+        const int old = atomicCAS(&tab[h + e], -1, id);
+        if (old == -1) return 1;
+        if (old == id) return 0;
+      }
+    }
+    h = (h + 4) & cap_mask;
   }
   spilled = true;
   uint32_t g = (hash_id(id ^ 0x5bd1e995) >> 5) & spill_mask;
@@ -531,8 +547,10 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   // keeps them in the LDS address space (ds_read/ds_write, not flat)
   float* TD = reinterpret_cast<float*>(base);
   int* TI = reinterpret_cast<int*>(base + 4 * a.ef_max);
-  int* vis = reinterpret_cast<int*>(base + 8 * a.ef_max);
-  int* cid = reinterpret_cast<int*>(base + 8 * a.ef_max + 4 * a.vis_cap);
+  // V starts 16-byte aligned (its buckets are read 16 bytes at a time)
+  const int t_bytes = (8 * a.ef_max + 15) & ~15;
+  int* vis = reinterpret_cast<int*>(base + t_bytes);
+  int* cid = reinterpret_cast<int*>(base + t_bytes + 4 * a.vis_cap);
   int* cflag = reinterpret_cast<int*>(cid + 64);
   float* wv = reinterpret_cast<float*>(cflag + 64);  // [rpad] (screening)
   float* pqv = wv + a.rpad;                          // [rpad] this query's Pq
@@ -1169,7 +1187,7 @@ hipError_t launch_codes(const KArgs& a, int code, bool pf, int blocks, int lds, 
 
 int wave_bytes(int ef_max, int vis_cap, int r, int m, int gate_in) {
   const int rpad = rpad_of(r);
-  int b = 8 * ef_max + 4 * vis_cap + 64 * 4 * 2 + 8 * rpad + (r > 0 ? 4 * m : 0);
+  int b = ((8 * ef_max + 15) & ~15) + 4 * vis_cap + 64 * 4 * 2 + 8 * rpad + (r > 0 ? 4 * m : 0);
   if (gate_in > 0) {
     // edge features [32][k1] and hidden activations [32][k2] in bf16, outputs [32]
     const GateLayout GL = gate_layout(r, 64);
