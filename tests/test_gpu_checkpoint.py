@@ -1,5 +1,5 @@
-"""Tables checkpoint round trip and the visited-set overflow error, on the
-GPU.  A search on imported tables must return exactly what it returns on
+"""Tables checkpoint round trip, the visited-set overflow error and the
+allocation-failure path, on the GPU.  A search on imported tables must return exactly what it returns on
 the handle that was exported; an image over other points or another graph,
 or with a damaged byte, is refused.  A visited set forced far below what a
 query needs must be reported as EOVERFLOW (every kernel still exits
@@ -96,4 +96,33 @@ def test_visited_overflow_is_an_error():
     ids2, _, ctr2 = api.finger_search(tab, _t(qs[:64]), mode=0, k=10, ef=256, entry=entry,
                                       visited_capacity=256, spill_capacity=8192)
     np.testing.assert_array_equal(ids.cpu().numpy(), ids2.cpu().numpy())
+    tab.close()
+
+
+def test_allocation_failure_is_enomem():
+    """With FINGER_FAULT_INJECT=alloc every device allocation of the library
+    fails: the table build and the graph construction (the calls that
+    allocate; searches and the exact kNN take a caller workspace) return
+    ENOMEM with a message naming the allocation, and release what they had
+    taken (a normal build afterwards succeeds and searches)."""
+    import os
+    from paper_2206_11408_amd import _lib as L
+    from paper_2206_11408_amd import api
+    _say("injected allocation failures -> ENOMEM")
+    data, qs, G, entry, _ = helpers.c1(nq=20)
+    dd, Gd = _t(data), _t(G)
+    os.environ["FINGER_FAULT_INJECT"] = "alloc"
+    try:
+        calls = (("build", lambda: api.finger_build_tables(dd, Gd, rank=8)),
+                 ("graph", lambda: api.finger_build_graph(dd, knn_k=8, max_degree=16, entry=entry)))
+        for name, call in calls:
+            with pytest.raises(L.FingerError) as e:
+                call()
+            assert e.value.status == L.FINGER_ENOMEM, name
+            assert "injected" in str(e.value), name
+    finally:
+        del os.environ["FINGER_FAULT_INJECT"]
+    tab = api.finger_build_tables(dd, Gd, rank=8)
+    ids, _, ctr = api.finger_search(tab, _t(qs), mode=1, k=10, ef=32, entry=entry)
+    assert (ids.cpu().numpy() >= 0).all()
     tab.close()

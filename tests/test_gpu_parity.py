@@ -93,6 +93,38 @@ def test_plain_search_parity_integer_pivots(api):
     np.testing.assert_array_equal(ctr.cpu().numpy()[:, :6], oc)
 
 
+def test_build_refuses_malformed_graph_rows(api):
+    """The build refuses a graph row with a repeated id, a self loop, an id
+    out of range or a gap before the -1 padding (EINVAL).  The search relies
+    on the first: neighbours of one row are distinct, so lanes never insert
+    one id into the visited set twice."""
+    from paper_2206_11408_amd import _lib as L
+    data, qs, G, entry, _ = helpers.c1(nq=10)
+    row = int(np.nonzero((G >= 0).sum(1) >= 3)[0][0])
+
+    def repeated(g):
+        g[row, 1] = g[row, 0]
+
+    def self_loop(g):
+        g[row, 0] = row
+
+    def out_of_range(g):
+        g[row, 0] = data.shape[0]
+
+    def gap(g):
+        g[row, 0] = -1
+
+    for name, edit in (("repeated id", repeated), ("self loop", self_loop), ("out of range", out_of_range),
+                       ("gap", gap)):
+        g = G.copy()
+        edit(g)
+        with pytest.raises(L.FingerError) as e:
+            api.finger_build_tables(_t(data), _t(g), rank=0)
+        assert e.value.status == L.FINGER_EINVAL, name
+        assert "graph" in str(e.value), name
+    api.finger_build_tables(_t(data), _t(G), rank=0).close()
+
+
 def test_tables_against_oracle(api):
     _say("tables c2-small r=16")
     data, qs, G, _, piv = helpers.c2_small()
