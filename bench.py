@@ -157,7 +157,7 @@ def c4_leg(a, log, tune_mod) -> dict:
         geo = {}
         if a.tune:
             ch = tune_mod.autotune(tab, d_q, base, repeats=2, cache_path=None)
-            geo = {k: ch[k] for k in ("waves_per_cu", "code_prefetch", "visited_capacity")}
+            geo = {k: ch[k] for k in ("waves_per_cu", "code_prefetch", "visited_capacity", "visited_probe")}
         p = api.search_params(**{**base, **geo})
         outb = (torch.empty((nq, 100), dtype=torch.int32, device=dev),
                 torch.empty((nq, 100), dtype=torch.float32, device=dev),
@@ -396,14 +396,15 @@ def main() -> int:
                 ch = dict(best)
             launch[(mode, id(tab), prefetch, entry)] = {k: ch[k] for k in
                                                         ("waves_per_cu", "persistent", "code_prefetch",
-                                                         "visited_capacity")}
+                                                         "visited_capacity", "visited_probe")}
             log(f"tuned launch mode={mode}: {launch[(mode, id(tab), prefetch, entry)]}")
         geo = launch.get((mode, id(tab), prefetch, entry), {})
         p = api.search_params(mode=mode, k=10, ef=ef, entry=entry, screen_layout=a.screen_layout, gate_band=band,
                               code_prefetch=geo.get("code_prefetch", prefetch),
                               waves_per_cu=geo.get("waves_per_cu", 0),
                               persistent=geo.get("persistent", 0),
-                              visited_capacity=geo.get("visited_capacity", 0))
+                              visited_capacity=geo.get("visited_capacity", 0),
+                              visited_probe=geo.get("visited_probe", 0))
         for _ in range(warmup):
             api.finger_search(tab, d_q, p, out=out, check=False)
         pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -431,7 +432,8 @@ def main() -> int:
                                    code_prefetch=geo.get("code_prefetch", prefetch),
                                    waves_per_cu=geo.get("waves_per_cu", 0),
                                    persistent=geo.get("persistent", 0),
-                                   visited_capacity=geo.get("visited_capacity", 0))
+                                   visited_capacity=geo.get("visited_capacity", 0),
+                              visited_probe=geo.get("visited_probe", 0))
             side = torch.cuda.Stream()
             side.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(side):

@@ -244,6 +244,11 @@ typedef struct finger_search_params {
                              default next_pow2(ef_max * max_degree) clamped
                              to [1024, 65536].  Together with the LDS table
                              it bounds |V| per query (status bit 0). */
+  int32_t visited_probe;  /* LDS slots a visited test examines before it
+                             continues in the spill table: a multiple of 4 in
+                             [4, 64]; 0 = default 24.  Fewer spill sooner but
+                             walk less of a nearly full table.  Results do not
+                             depend on it. */
   int32_t code_prefetch; /* FINGER mode: 1 = request every slot's edge code
                             together with the adjacency row (one round trip
                             fewer; also reads the codes of visited and

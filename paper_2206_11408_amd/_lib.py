@@ -59,7 +59,7 @@ class SearchParams(C.Structure):
         ("warmup", C.c_int32), ("k_max", C.c_int32),
         ("k_per_query", C.c_void_p), ("ef_per_query", C.c_void_p),
         ("ef_max", C.c_int32), ("persistent", C.c_int32), ("waves_per_cu", C.c_int32),
-        ("visited_capacity", C.c_int32), ("spill_capacity", C.c_int32),
+        ("visited_capacity", C.c_int32), ("spill_capacity", C.c_int32), ("visited_probe", C.c_int32),
         ("code_prefetch", C.c_int32), ("ef_classes", C.c_int32), ("gate_band", C.c_float),
         ("screen_layout", C.c_int32),
         ("log_features", C.c_void_p), ("log_targets", C.c_void_p),

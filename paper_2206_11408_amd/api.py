@@ -144,7 +144,7 @@ def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
                   k_per_query=None, ef_per_query=None, ef_max=0, persistent=0,
                   waves_per_cu=0, visited_capacity=0, code_prefetch=0,
                   log=None, spill_capacity=0, screen_layout=0, ef_classes=0,
-                  gate_band=0.0) -> L.SearchParams:
+                  gate_band=0.0, visited_probe=0) -> L.SearchParams:
     p = L.SearchParams()
     L.load().finger_search_params_init(C.byref(p))
     p.mode, p.k, p.ef, p.entry, p.warmup = mode, k, ef, entry, warmup
@@ -154,6 +154,7 @@ def search_params(mode=L.MODE_PLAIN, k=10, ef=64, entry=0, warmup=5, k_max=None,
     p.ef_max, p.persistent = ef_max, persistent
     p.waves_per_cu, p.visited_capacity = waves_per_cu, visited_capacity
     p.spill_capacity = spill_capacity
+    p.visited_probe = visited_probe
     p.screen_layout = screen_layout
     p.ef_classes = ef_classes
     p.gate_band = gate_band

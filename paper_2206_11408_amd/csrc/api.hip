@@ -411,6 +411,8 @@ int plan_search(const Tables* t, int64_t nq, const finger_search_params* p, Plan
     return fail(FINGER_EINVAL, "screen_layout = %d must be 0, 1 or 2", p->screen_layout);
   if (vis_cap < 256 || (vis_cap & (vis_cap - 1)) != 0)
     return fail(FINGER_EINVAL, "visited_capacity = %d must be a power of two >= 256", vis_cap);
+  if (p->visited_probe != 0 && (p->visited_probe < 4 || p->visited_probe > 64 || (p->visited_probe & 3) != 0))
+    return fail(FINGER_EINVAL, "visited_probe = %d must be 0 or a multiple of 4 in [4, 64]", p->visited_probe);
   const int gate_in = p->mode == FINGER_MODE_GATED ? t->gate_in : 0;
   const int r_used = p->mode == FINGER_MODE_PLAIN ? 0 : t->r;
   const int lds_wave = search_lds_bytes(ef_max, vis_cap, r_used, t->m, gate_in);
@@ -552,6 +554,7 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
   L.spill = spill;
   L.spill_slots_per_wave = pl.spill_slots;
   L.vis_cap = pl.vis_cap;
+  L.vis_probe = p->visited_probe ? p->visited_probe : 24;
   L.waves = pl.waves;
   L.persistent = p->persistent;
   L.prefetch = p->code_prefetch > 0;

@@ -167,6 +167,7 @@ struct SearchLaunch {
   int32_t* spill;
   int spill_slots_per_wave;
   int vis_cap;
+  int vis_probe;    // LDS slots a visited test examines before the spill table
   int waves;        // grid size in waves
   int persistent;
   int prefetch;     // issue every slot's edge code with the adjacency row

@@ -9,7 +9,7 @@
 //          (hint) is expanded, so the search for the next centre starts
 //          there.
 //   V      the visited set: open addressing with linear probing over
-//          buckets of four slots; a probe run longer than kLdsProbes slots
+//          buckets of four slots; a probe run longer than vis_probe slots
 //          continues in a per-wave table in the workspace; when both are
 //          full the query reports an overflow.
 //   w      P q_res for the current centre (screening only).
@@ -44,7 +44,7 @@ namespace {
 constexpr uint32_t kExpanded = 0x80000000u;
 // FINGER search that also writes the gate-training log (internal mode)
 constexpr int kModeLog = 3;
-constexpr int kLdsProbes = 24;
+
 // code elements one lane holds: 32 (128 bytes of fp32, 64 of bf16, 32 of
 // fp8), so a rank-64 code is two lanes and a screen of 32 slots one pass
 template <int CODE>
@@ -96,6 +96,7 @@ struct KArgs {
   int32_t* spill;
   int spill_slots;
   int vis_cap;
+  int vis_buckets;  // LDS buckets of four slots a visited test examines
   int waves_per_block;
   int coalesced;  // FINGER mode: use the coalesced screen where it applies
   int lds_wave_bytes;
@@ -125,12 +126,12 @@ __device__ __forceinline__ uint32_t hash_id(int id) { return (uint32_t)id * 2654
 // Slots only ever fill, so an id is always in the first empty slot of its
 // probe sequence or before it; lanes with the same id see the same bucket
 // and race for the same slot, so an id is inserted once.
-__device__ __forceinline__ int visit(int id, int* __restrict__ tab, uint32_t cap_mask,
+__device__ __forceinline__ int visit(int id, int* __restrict__ tab, uint32_t cap_mask, int buckets,
                                      int* __restrict__ spill, uint32_t spill_mask,
                                      bool& spilled, bool& overflow) {
   uint32_t h = (hash_id(id) >> 7) & cap_mask & ~3u;
 #pragma unroll 1
-  for (int p = 0; p < kLdsProbes / 4; ++p) {
+  for (int p = 0; p < buckets; ++p) {
     const int4 b = *reinterpret_cast<const int4*>(tab + h);
     if (b.x == id || b.y == id || b.z == id || b.w == id) return 0;
     const int v[4] = {b.x, b.y, b.z, b.w};
@@ -662,7 +663,7 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
 
     const int entry = a.entries ? a.entries[qi] : a.entry;
     if (l == 0) {
-      visit(entry, vis, cap_mask, spill, spill_mask, spilled, overflow);
+      visit(entry, vis, cap_mask, a.vis_buckets, spill, spill_mask, spilled, overflow);
       cid[0] = entry;
     }
     wave_lds_sync();
@@ -757,7 +758,7 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       }
       // 3. visited test-and-set
       int isnew = 0;
-      if (nb >= 0) isnew = visit(nb, vis, cap_mask, spill, spill_mask, spilled, overflow);
+      if (nb >= 0) isnew = visit(nb, vis, cap_mask, a.vis_buckets, spill, spill_mask, spilled, overflow);
       const uint64_t newm = ballot(isnew != 0);
       const int S = popc64(newm);
       n_vis += S;
@@ -1260,6 +1261,7 @@ hipError_t launch_search(const Tables& t, const SearchLaunch& L, hipStream_t s) 
   a.spill = L.spill;
   a.spill_slots = L.spill_slots_per_wave;
   a.vis_cap = L.vis_cap;
+  a.vis_buckets = L.vis_probe / 4;
   a.log_x = L.log_x;
   a.log_y = L.log_y;
   a.log_cap = L.log_cap;

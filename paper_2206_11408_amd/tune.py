@@ -31,17 +31,19 @@ def _key(tables: api.Tables, mode: int, ef_max: int, mixed: bool) -> str:
 
 def candidates(mode: int, ef_max: int = 64, mixed: bool = False):
     # visited-set capacity trades LDS per wave (resident waves) against probe
-    # length and spills; the library default is 2048.  Searches with per-query
-    # K or ef always run persistent launches.
-    vis = (1024, 2048, 4096)
+    # length and spills; the library default is 2048.  With the small table a
+    # shorter LDS probe (8 slots instead of 24) spills sooner but walks less
+    # of a nearly full table.  Searches with per-query K or ef always run
+    # persistent launches.
+    vis = ((1024, 24), (1024, 8), (2048, 24), (4096, 24))
     out = []
     for wpc in (8, 12, 16, 20, 24, 32):
         for persistent in ((1,) if mixed else (0, 1)):
             pfs = (0,) if mode == L.MODE_PLAIN else (-1, 1)
             for pf in pfs:
-                for vc in vis:
+                for vc, vp in vis:
                     out.append({"waves_per_cu": wpc, "persistent": persistent, "code_prefetch": pf,
-                                "visited_capacity": vc})
+                                "visited_capacity": vc, "visited_probe": vp})
     return out
 
 

@@ -157,7 +157,9 @@ def test_results_independent_of_launch_geometry(api, mode):
     base = dict(mode=mode, k=10, ef=48, entry=-1)
     ref = [x.cpu().numpy() for x in api.finger_search(tab, _t(qs), **base)]
     variants = [dict(waves_per_cu=1), dict(waves_per_cu=2, persistent=1), dict(persistent=1),
-                dict(visited_capacity=256), dict(visited_capacity=256, persistent=1, waves_per_cu=3)]
+                dict(visited_capacity=256), dict(visited_capacity=256, persistent=1, waves_per_cu=3),
+                dict(visited_capacity=256, visited_probe=4), dict(visited_probe=64),
+                dict(visited_capacity=1024, visited_probe=8, persistent=1)]
     if mode:
         variants += [dict(code_prefetch=1), dict(code_prefetch=-1, persistent=1)]
     for v in variants:
