@@ -121,11 +121,14 @@ __device__ __forceinline__ uint32_t hash_id(int id) { return (uint32_t)id * 2654
 // both tables were exhausted (the id is then treated as visited).
 // The LDS table is probed linearly in buckets of four slots: one 16-byte
 // read examines a bucket; an id present there is visited; otherwise the id
-// goes into the bucket's first empty slot (compare-and-swap, the next empty
-// one if another lane took it), and only a full bucket moves the probe on.
-// Slots only ever fill, so an id is always in the first empty slot of its
-// probe sequence or before it; lanes with the same id see the same bucket
-// and race for the same slot, so an id is inserted once.
+// goes into the bucket's first empty slot, and only a full bucket moves the
+// probe on.  All lanes claim their slots in the same compare-and-swap (one
+// LDS round trip for the wave, whichever slot each lane needs); lanes of one
+// bucket saw the same slots empty, so a lane that lost its slot to another
+// lane tries the next one.  Slots only ever fill, so an id is always in the
+// first empty slot of its probe sequence or before it; lanes with the same
+// id see the same bucket and race for the same slot, so an id is inserted
+// once.
 __device__ __forceinline__ int visit(int id, int* __restrict__ tab, uint32_t cap_mask, int buckets,
                                      int* __restrict__ spill, uint32_t spill_mask,
                                      bool& spilled, bool& overflow) {
@@ -133,15 +136,12 @@ __device__ __forceinline__ int visit(int id, int* __restrict__ tab, uint32_t cap
 #pragma unroll 1
   for (int p = 0; p < buckets; ++p) {
     const int4 b = *reinterpret_cast<const int4*>(tab + h);
-    if (b.x == id || b.y == id || b.z == id || b.w == id) return 0;
-    const int v[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (v[e] == -1) {
-        const int old = atomicCAS(&tab[h + e], -1, id);
-        if (old == -1) return 1;
-        if (old == id) return 0;
-      }
+    if ((b.x == id) | (b.y == id) | (b.z == id) | (b.w == id)) return 0;
+#pragma unroll 1
+    for (int e = b.x == -1 ? 0 : (b.y == -1 ? 1 : (b.z == -1 ? 2 : (b.w == -1 ? 3 : 4))); e < 4; ++e) {
+      const int old = atomicCAS(&tab[h + e], -1, id);
+      if (old == -1) return 1;
+      if (old == id) return 0;
     }
     h = (h + 4) & cap_mask;
   }
