@@ -114,6 +114,20 @@ struct KArgs {
   int64_t* log_count;
 };
 
+// Raw buffer resources (stride 0): the fourth descriptor word for gfx9-family
+// parts, and a byte offset past any block the kernels describe (such a load
+// returns zeros without touching memory).
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kBufPastEnd = 0x40000000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kBufWord3);
+}
+// 4-byte element i of a buffer, or zero when !valid (no memory access)
+__device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, int i, bool valid) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, valid ? 4 * i : kBufPastEnd, 0, 0);
+}
+
 __device__ __forceinline__ uint32_t hash_id(int id) { return (uint32_t)id * 2654435761u; }
 
 // Exact membership test-and-insert.  Returns 1 if id was new, 0 if already
@@ -396,23 +410,21 @@ __device__ __forceinline__ float exact_dists(const KArgs& a, const float4* qv, c
     }
     return mine;
   }
+  // Other shapes: every lane loads, with no branch (so that the waits count
+  // exactly and one pass's sums overlap the next pass's loads): slots past
+  // cnt load the first id's vector again, pieces past m reload the last
+  // piece of the vector and are zeroed after the load.
   for (int p0 = 0; p0 < cnt; p0 += NP * NPP) {
     float4 xv[NP][T4];
-    int p[NP];
-#pragma unroll
-    for (int h = 0; h < NP; ++h) p[h] = p0 + h * NPP + slot;
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
-      if (p[h] < cnt) {
-        const float4* x4 = reinterpret_cast<const float4*>(a.data + (int64_t)ids_lds[p[h]] * a.m);
+      const int ph = p0 + h * NPP + slot;
+      const float4* x4 = reinterpret_cast<const float4*>(a.data + (int64_t)ids_lds[ph < cnt ? ph : 0] * a.m);
 #pragma unroll
-        for (int t = 0; t < T4; ++t) {
-          const int j = lg + G * t;
-          xv[h][t] = j < a.m4 ? x4[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < T4; ++t) xv[h][t] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int t = 0; t < T4; ++t) {
+        const int j = lg + G * t;
+        const float4 v = x4[j < a.m4 ? j : a.m4 - 1];
+        xv[h][t] = j < a.m4 ? v : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
 #pragma unroll
@@ -702,8 +714,11 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
 
       const bool screening = (MODE != FINGER_MODE_PLAIN) && n_exp > a.warmup && tn == ef_eff;
       // 2. one round trip: adjacency (+ screening inputs)
-      int nb = -1;
-      if (l < a.deg) nb = a.graph[(int64_t)cur * a.deg + l];
+      // (buffer loads answer lanes past the degree with zeros and no access;
+      // with no branch around them the waits below count exactly which
+      // loads they need)
+      int nb = (int)buf_u32(buf_rsrc(a.graph + (int64_t)cur * a.deg, 4 * a.deg), l, l < a.deg);
+      if (l >= a.deg) nb = -1;
       float al = 0.f, rh = 0.f, ccv = 0.f;
       // P c of the centre, element l + 64 t in pcv[t] (rpad <= 256), read in
       // this round trip so that forming w below waits on no memory access
@@ -718,29 +733,35 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
 #pragma unroll
       for (int i = 0; i < kNI; ++i) craw[i] = make_uint4(0u, 0u, 0u, 0u);
       if constexpr (kCoal) {
-        if (screening) {
-          if (myslot < a.deg) {
-            al = a.alpha[(int64_t)cur * a.deg + myslot];
-            rh = a.rho[(int64_t)cur * a.deg + myslot];
-          }
-          ccv = a.cc[cur];
-          const float4* pc4 = reinterpret_cast<const float4*>(a.pc + (int64_t)cur * a.rpad + lp * kFE);
+        // requested on every expansion, with every lane masked off when this
+        // one does not screen: no branch, so the wait for the row below
+        // leaves these in flight through the visited test
+        al = __uint_as_float(buf_u32(buf_rsrc(a.alpha + (int64_t)cur * a.deg, 4 * a.deg), myslot,
+                                     screening && myslot < a.deg));
+        rh = __uint_as_float(buf_u32(buf_rsrc(a.rho + (int64_t)cur * a.deg, 4 * a.deg), myslot,
+                                     screening && myslot < a.deg));
+        ccv = __uint_as_float(buf_u32(buf_rsrc(a.cc + cur, 4), 0, screening));
+        const __amdgpu_buffer_rsrc_t pcr = buf_rsrc(a.pc + (int64_t)cur * a.rpad, 4 * a.rpad);
 #pragma unroll
-          for (int t = 0; t < kFE / 4; ++t) {
-            const float4 v = pc4[t];
-            pcf[4 * t] = v.x;
-            pcf[4 * t + 1] = v.y;
-            pcf[4 * t + 2] = v.z;
-            pcf[4 * t + 3] = v.w;
-          }
-          if constexpr (CODE == FINGER_CODE_FP8E4M3) sclv = a.scale[cur];
-          if constexpr (PREFETCH) {
-            const uint4* cb = reinterpret_cast<const uint4*>(static_cast<const char*>(a.codes) +
-                                                             (int64_t)cur * a.deg * (LC * 16));
+        for (int t = 0; t < kFE / 4; ++t) {
+          const float4 v = __builtin_bit_cast(
+              float4, __builtin_amdgcn_raw_buffer_load_b128(pcr, screening ? 4 * (lp * kFE + 4 * t) : kBufPastEnd,
+                                                            0, 0));
+          pcf[4 * t] = v.x;
+          pcf[4 * t + 1] = v.y;
+          pcf[4 * t + 2] = v.z;
+          pcf[4 * t + 3] = v.w;
+        }
+        if constexpr (CODE == FINGER_CODE_FP8E4M3)
+          sclv = __uint_as_float(buf_u32(buf_rsrc(a.scale + cur, 4), 0, screening));
+        if constexpr (PREFETCH) {
+          const __amdgpu_buffer_rsrc_t cbr = buf_rsrc(
+              static_cast<const char*>(a.codes) + (int64_t)cur * a.deg * (LC * 16), a.deg * (LC * 16));
 #pragma unroll
-            for (int i = 0; i < kNI; ++i)
-              if (i * kSPI + lg < a.deg) craw[i] = cb[64 * i + l];
-          }
+          for (int i = 0; i < kNI; ++i)
+            craw[i] = __builtin_bit_cast(
+                uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                           cbr, screening && i * kSPI + lg < a.deg ? (64 * i + l) * 16 : kBufPastEnd, 0, 0));
         }
       } else if constexpr (MODE != FINGER_MODE_PLAIN) {
         if (screening) {
@@ -774,12 +795,19 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
           n_scr += S;
           ++n_prep;
           if constexpr (!PREFETCH) {
-            const uint4* cb = reinterpret_cast<const uint4*>(static_cast<const char*>(a.codes) +
-                                                             (int64_t)cur * a.deg * (LC * 16));
+            // buffer loads over this node's code block: a lane whose slot is
+            // not new reads past the block's end, which the hardware answers
+            // with zeros and no memory access.  No branch surrounds the loads,
+            // so forming w below waits only for the row's screening inputs
+            // while the codes are in flight.
+            const __amdgpu_buffer_rsrc_t cbr = buf_rsrc(
+                static_cast<const char*>(a.codes) + (int64_t)cur * a.deg * (LC * 16), a.deg * (LC * 16));
+            // (newm has no bit at or past the row's degree: those lanes hold no id)
 #pragma unroll
             for (int i = 0; i < kNI; ++i) {
-              const int slot = i * kSPI + lg;
-              if (slot < a.deg && ((newm >> slot) & 1ull)) craw[i] = cb[64 * i + l];
+              const bool ld = (newm >> (i * kSPI + lg)) & 1ull;
+              craw[i] = __builtin_bit_cast(
+                  uint4, __builtin_amdgcn_raw_buffer_load_b128(cbr, ld ? (64 * i + l) * 16 : kBufPastEnd, 0, 0));
             }
           }
           // query side (Section 3.2 and Supplementary G), as below; w is
