@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -54,10 +55,16 @@ def algorithmic_bytes(ctr: np.ndarray, m: int, deg: int, r: int, code_bytes: int
 
 
 def kernel_source_hash() -> str:
+    """Hash of the search kernel's code: comments, trailing blanks and blank
+    lines are dropped, so that editing a comment keeps counters taken on the
+    same code valid."""
     h = hashlib.sha256()
     for f in ("search.hip", "device_common.h"):
-        with open(os.path.join(ROOT, "paper_2206_11408_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2206_11408_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

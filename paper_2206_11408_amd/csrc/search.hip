@@ -2,12 +2,14 @@
 // search (Algorithm 4 with the estimate of Algorithm 3 in the factorized
 // form of Supplementary G), one wavefront per query.
 //
-// Per-wave state lives in LDS:
+// Per-wave state:
 //   T      the best ef_eff keys (d2, id) found so far, sorted; bit 31 of an
 //          id marks "expanded".  The unexpanded entries of T play the role
-//          of the candidate queue C.  Every entry below a running index
-//          (hint) is expanded, so the search for the next centre starts
-//          there.
+//          of the candidate queue C.  Up to ef_max = 64, T sits in registers
+//          (lane i holds entry i); longer lists sit in LDS, where every entry
+//          below a running index (hint) is expanded, so the search for the
+//          next centre starts there.
+// and in LDS:
 //   V      the visited set: open addressing with linear probing over
 //          buckets of four slots; a probe run longer than vis_probe slots
 //          continues in a per-wave table in the workspace; when both are
@@ -30,8 +32,12 @@
 //      32 consecutive elements of one slot's code;
 //   5. gather the survivors' vectors (G lanes per vector, float4 loads) and
 //      reduce (q - x)^2 across the group;
-//   6. merge admitted keys into T in place by rank (ballots over T,
-//      broadcast reads of the few new keys), no sort.
+//   6. merge admitted keys into T by rank (ballots over T, broadcast reads
+//      of the few new keys), no sort.
+// Loads whose lanes are conditional are raw buffer loads with the masked
+// lanes sent past the end of the buffer, not loads inside branches: the
+// compiler merges the wait counts of the paths around a branched load,
+// which made later work wait for loads it does not use.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -680,36 +686,54 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
     }
     wave_lds_sync();
     const float d_entry = exact_dists<G, T4, 1>(a, qv, qlds, cid, 1);
-    if (l == 0) {
+    // T lives in registers when it fits one entry per lane (ef_max <= 64):
+    // lane i holds entry i as td (distance) and ti (id with the expanded
+    // bit); selection and merge then read no memory.  Larger lists live in
+    // LDS (TD, TI) and are scanned and merged in blocks of 64.
+    const bool treg = a.ef_max <= 64;
+    float td = d_entry;
+    int ti = entry;
+    if (!treg && l == 0) {
       TD[0] = d_entry;
       TI[0] = entry;
     }
     wave_lds_sync();
     int tn = 1;
     int n_exp = 0, n_exact = 1, n_scr = 0, n_skip = 0, n_vis = 1, n_prep = 0;
-    int hint = 0;  // every entry of T below this index is expanded
+    int hint = 0;  // LDS list: every entry of T below this index is expanded
 
     while (true) {
-      // 1. the best unexpanded entry of T, scanning from the block that
-      // holds index hint
+      // 1. the best unexpanded entry of T (in LDS: scanning from the block
+      // that holds index hint)
       int j = -1, cur = -1;
-      for (int b0 = hint & ~63; b0 < tn; b0 += 64) {
-        const int i = b0 + l;
-        const int raw = i < tn ? TI[i] : (int)kExpanded;
-        const uint64_t bm = ballot(((uint32_t)raw & kExpanded) == 0u);
-        if (bm) {
-          const int s0 = __ffsll((unsigned long long)bm) - 1;
-          j = b0 + s0;
-          cur = __builtin_amdgcn_readlane(raw, s0);
-          break;
+      float dcur, ub2;
+      if (treg) {
+        const uint64_t bm = ballot(l < tn && ((uint32_t)ti & kExpanded) == 0u);
+        if (bm == 0ull) break;
+        j = __ffsll((unsigned long long)bm) - 1;
+        cur = __builtin_amdgcn_readlane(ti, j);
+        dcur = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(td), j));
+        ub2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(td), tn - 1));
+        if (l == j) ti = (int)((uint32_t)ti | kExpanded);
+      } else {
+        for (int b0 = hint & ~63; b0 < tn; b0 += 64) {
+          const int i = b0 + l;
+          const int raw = i < tn ? TI[i] : (int)kExpanded;
+          const uint64_t bm = ballot(((uint32_t)raw & kExpanded) == 0u);
+          if (bm) {
+            const int s0 = __ffsll((unsigned long long)bm) - 1;
+            j = b0 + s0;
+            cur = __builtin_amdgcn_readlane(raw, s0);
+            break;
+          }
         }
+        if (j < 0) break;
+        hint = j + 1;
+        dcur = uniform_f(TD[j]);
+        ub2 = uniform_f(TD[tn - 1]);
+        wave_lds_sync();
+        if (l == 0) TI[j] = (int)((uint32_t)cur | kExpanded);
       }
-      if (j < 0) break;
-      hint = j + 1;
-      const float dcur = uniform_f(TD[j]);
-      const float ub2 = uniform_f(TD[tn - 1]);
-      wave_lds_sync();
-      if (l == 0) TI[j] = (int)((uint32_t)cur | kExpanded);
       ++n_exp;
 
       const bool screening = (MODE != FINGER_MODE_PLAIN) && n_exp > a.warmup && tn == ef_eff;
@@ -1033,8 +1057,10 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       uint64_t key = ~0ull;
       bool adm = false;
       bool was_skipped = false;
-      const uint64_t worst_key = make_key(uniform_f(TD[tn - 1]),
-                                          uniform_i((int)((uint32_t)TI[tn - 1] & ~kExpanded)));
+      const uint64_t worst_key =
+          treg ? make_key(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(td), tn - 1)),
+                          (int)((uint32_t)__builtin_amdgcn_readlane(ti, tn - 1) & ~kExpanded))
+               : make_key(uniform_f(TD[tn - 1]), uniform_i((int)((uint32_t)TI[tn - 1] & ~kExpanded)));
       if (l < S2) {
         if (logging) {
           was_skipped = cflag[l] != 0;
@@ -1058,6 +1084,37 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       // before anything lands on it (entries only move right); the blocks
       // wholly below the smallest new key keep their places untouched.
       int my_pos = 0;
+      if (treg) {
+        // T in registers: a new key's place is (new keys below it) + (T keys
+        // below it); lane p then takes the new key placed at p, or else T
+        // entry p - (new keys placed below p), read across lanes
+        const uint64_t tk = l < tn ? make_key(td, (int)((uint32_t)ti & ~kExpanded)) : ~0ull;
+        for (uint64_t mm = am; mm; mm &= mm - 1ull) {
+          const int src = __ffsll((unsigned long long)mm) - 1;
+          const uint64_t kj = readlane_u64(key, src);
+          my_pos += kj < key ? 1 : 0;
+          const int below = popc64(ballot(tk < kj));
+          if (l == src) my_pos += below;
+        }
+        uint64_t placed = 0ull, nk = 0ull;
+        for (uint64_t mm = am; mm; mm &= mm - 1ull) {
+          const int src = __ffsll((unsigned long long)mm) - 1;
+          const int pos = __builtin_amdgcn_readlane(my_pos, src);
+          if (pos < ef_eff) {
+            placed |= 1ull << pos;
+            const uint64_t kj = readlane_u64(key, src);
+            if (l == pos) nk = kj;
+          }
+        }
+        const int from = l - popc64(placed & ((1ull << l) - 1ull));
+        const float od = __shfl(td, from, 64);
+        const int oi = __shfl(ti, from, 64);
+        const bool mine_new = ((placed >> l) & 1ull) != 0ull;
+        td = mine_new ? key_d2(nk) : od;
+        ti = mine_new ? key_id(nk) : oi;
+        tn = min(tn + NA, ef_eff);
+        continue;
+      }
       uint64_t kmin = ~0ull;
       int kmin_src = 0;
       for (uint64_t mm = am; mm; mm &= mm - 1ull) {
@@ -1110,8 +1167,9 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
         int id = -1;
         float d = __int_as_float(0x7f800000);
         if (jx < k && jx < tn) {
-          id = (int)((uint32_t)TI[jx] & ~kExpanded);
-          d = TD[jx];
+          // (T in registers: tn <= 64, so jx is this lane's entry)
+          id = (int)((uint32_t)(treg ? ti : TI[jx]) & ~kExpanded);
+          d = treg ? td : TD[jx];
         }
         a.out_ids[qi * a.k_max + jx] = id;
         a.out_dist[qi * a.k_max + jx] = d;
