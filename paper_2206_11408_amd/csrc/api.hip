@@ -524,9 +524,10 @@ int finger_search(const finger_tables* th, const float* queries, int64_t nq,
     HIPCHK(launch_normalize_rows(queries, nq, t->m, qn, s));
     queries = qn;
   }
-  // fill kernels rather than memsets: a caller may capture this call in a graph
+  // a fill kernel rather than a memset: a caller may capture this call in a
+  // graph.  The visited-set spill tables need no fill: each wave empties its
+  // own the first time it needs it.
   HIPCHK(launch_fill_u32(queue, 0u, kMaxEfClasses, s));
-  HIPCHK(launch_fill_u32(spill, 0xFFFFFFFFu, (pl.off_lists - pl.off_spill) / 4, s));
   const bool need_prep = p->mode != FINGER_MODE_PLAIN || p->entry == FINGER_ENTRY_PIVOT;
   if (need_prep)
     HIPCHK(launch_query_prep(*t, queries, nq, qq, pq, p->entry == FINGER_ENTRY_PIVOT ? ent : nullptr,

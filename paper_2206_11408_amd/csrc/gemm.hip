@@ -249,17 +249,37 @@ __device__ __forceinline__ b8v load_query_frag(const float* __restrict__ Q, int6
   return r;
 }
 
-// Fold one 16x16 score tile into the per-lane running minima (pn = |p|^2 of
-// this lane's column, loaded with the tile).
-__device__ __forceinline__ void fold_tile(const f4v& acc, int col, int npiv, float pn,
-                                          uint64_t best[4]) {
-  if (col >= npiv) return;
+// Per-lane running minima of four score rows: the lowest score and its
+// pivot.  Columns reach a lane in increasing order, so a strict comparison
+// keeps the smaller pivot of equal scores, which is the order of the
+// (score, pivot) keys built at the end (-0 and +0 compare equal, as their
+// keys do).
+struct PivBest {
+  float s[4];
+  int c[4];
+  __device__ __forceinline__ void init() {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const uint64_t k = ((uint64_t)order_bits(pn - 2.f * acc[v]) << 32) | (uint32_t)col;
-    best[v] = k < best[v] ? k : best[v];
+    for (int v = 0; v < 4; ++v) {
+      s[v] = __int_as_float(0x7f800000);
+      c[v] = -1;
+    }
   }
-}
+  // one 16x16 score tile (pn = |p|^2 of this lane's column, loaded with the tile)
+  __device__ __forceinline__ void fold(const f4v& acc, int col, int npiv, float pn) {
+    if (col >= npiv) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float sc = pn - 2.f * acc[v];
+      if (sc < s[v] || c[v] < 0) {
+        s[v] = sc;
+        c[v] = col;
+      }
+    }
+  }
+  __device__ __forceinline__ uint64_t key(int v) const {
+    return c[v] < 0 ? ~0ull : (((uint64_t)order_bits(s[v]) << 32) | (uint32_t)c[v]);
+  }
+};
 
 // grid: ceil(nq / kPivRows) * kPivSplit waves, 4 per block; PB [npad][kpad] bf16
 // and pnorm [npad], npad = kPivSplit * range with range a multiple of 32,
@@ -284,11 +304,9 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lk = 8 * (l >> 4);
   const int c_beg = split * range;
-  uint64_t best[NT][4];
+  PivBest best[NT];
 #pragma unroll
-  for (int u = 0; u < NT; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) best[u][v] = ~0ull;
+  for (int u = 0; u < NT; ++u) best[u].init();
   if constexpr (KS > 0) {
     b8v a[NT][KS];
 #pragma unroll
@@ -318,7 +336,7 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
 #pragma unroll
         for (int u = 0; u < NT; ++u) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], bx[i], c[u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < NT; ++u) fold_tile(c[u], c_beg + t + lr, npiv, px, best[u]);
+      for (int u = 0; u < NT; ++u) best[u].fold(c[u], c_beg + t + lr, npiv, px);
       // next tile pair (the last iteration reloads its own first tile, unused)
       const int tn = t + 32 < range ? t + 32 : t;
 #pragma unroll
@@ -332,7 +350,7 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
 #pragma unroll
         for (int u = 0; u < NT; ++u) c[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u][i], by[i], c[u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < NT; ++u) fold_tile(c[u], c_beg + t + 16 + lr, npiv, py, best[u]);
+      for (int u = 0; u < NT; ++u) best[u].fold(c[u], c_beg + t + 16 + lr, npiv, py);
     }
   } else {
     // long vectors: the k dimension is walked in chunks of kPivKs steps whose
@@ -376,7 +394,7 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
         const int col = c_beg + 16 * (t0 + g) + lr;
         const float pn = pnorm[col];
 #pragma unroll
-        for (int u = 0; u < NT; ++u) fold_tile(c[g][u], col, npiv, pn, best[u]);
+        for (int u = 0; u < NT; ++u) best[u].fold(c[g][u], col, npiv, pn);
       }
     }
   }
@@ -385,7 +403,7 @@ __global__ void __launch_bounds__(256) k_pivot_scores(const float* __restrict__ 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       // row 4(l/16)+v of tile u: its 16 stripe minima, ascending
-      const uint64_t srt = sort16(best[u][v]);
+      const uint64_t srt = sort16(best[u].key(v));
       const int64_t row = q0 + 16 * u + 4 * (l >> 4) + v;
       if (lr < kPivKeep && row < nq) cand[row * kPivCand + split * kPivKeep + lr] = srt;
     }
@@ -428,11 +446,9 @@ __global__ void __launch_bounds__(256) k_pivot_scores_lds(const float* __restric
   const int arow = tid >> 2, acol = 8 * (tid & 3);
   const int64_t aq = q0 + arow;
   const float* asrc = Q + (aq < nq ? aq : 0) * (int64_t)m;
-  uint64_t best[4][4];
+  PivBest best[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) best[i][v] = ~0ull;
+  for (int i = 0; i < 4; ++i) best[i].init();
   const b8v zero8 = b8v{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
                         (__bf16)0.f, (__bf16)0.f};
   for (int pass = 0; pass < range; pass += kPlP) {
@@ -496,7 +512,7 @@ __global__ void __launch_bounds__(256) k_pivot_scores_lds(const float* __restric
         const int col = c_beg + pass + 64 * w + 16 * j + lr;
         const float pn = pnorm[col];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) fold_tile(acc[i][j], col, npiv, pn, best[i]);
+        for (int i = 0; i < 4; ++i) best[i].fold(acc[i][j], col, npiv, pn);
       }
     }
     __syncthreads();  // the next pass restages the slabs
@@ -506,7 +522,7 @@ __global__ void __launch_bounds__(256) k_pivot_scores_lds(const float* __restric
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) S[((16 * i + 4 * (l >> 4) + v) * 4 + w) * 16 + lr] = best[i][v];
+    for (int v = 0; v < 4; ++v) S[((16 * i + 4 * (l >> 4) + v) * 4 + w) * 16 + lr] = best[i].key(v);
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < 4; ++it) {

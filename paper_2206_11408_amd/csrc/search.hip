@@ -136,9 +136,10 @@ __device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, int i, boo
 
 __device__ __forceinline__ uint32_t hash_id(int id) { return (uint32_t)id * 2654435761u; }
 
-// Exact membership test-and-insert.  Returns 1 if id was new, 0 if already
-// visited; sets spilled when the global table was touched, overflow when
-// both tables were exhausted (the id is then treated as visited).
+// Exact membership test-and-insert.  visit_lds returns 1 if id was new, 0
+// if already visited, -1 if its probe run in LDS is full (visit_spill then
+// continues it in the workspace table: it sets spilled, and overflow when
+// that table is exhausted too, the id then treated as visited).
 // The LDS table is probed linearly in buckets of four slots: one 16-byte
 // read examines a bucket; an id present there is visited; otherwise the id
 // goes into the bucket's first empty slot, and only a full bucket moves the
@@ -149,9 +150,7 @@ __device__ __forceinline__ uint32_t hash_id(int id) { return (uint32_t)id * 2654
 // first empty slot of its probe sequence or before it; lanes with the same
 // id see the same bucket and race for the same slot, so an id is inserted
 // once.
-__device__ __forceinline__ int visit(int id, int* __restrict__ tab, uint32_t cap_mask, int buckets,
-                                     int* __restrict__ spill, uint32_t spill_mask,
-                                     bool& spilled, bool& overflow) {
+__device__ __forceinline__ int visit_lds(int id, int* __restrict__ tab, uint32_t cap_mask, int buckets) {
   uint32_t h = (hash_id(id) >> 7) & cap_mask & ~3u;
 #pragma unroll 1
   for (int p = 0; p < buckets; ++p) {
@@ -165,6 +164,20 @@ __device__ __forceinline__ int visit(int id, int* __restrict__ tab, uint32_t cap
     }
     h = (h + 4) & cap_mask;
   }
+  return -1;
+}
+
+// Empty a wave's workspace table (slots: a power of two >= 64, the table
+// 16-byte aligned), visible to the wave's later atomics.
+__device__ __forceinline__ void clear_spill(int* spill, int slots) {
+  int4* t4 = reinterpret_cast<int4*>(spill);
+  for (int i = lane_id(); i < slots / 4; i += 64) t4[i] = make_int4(-1, -1, -1, -1);
+  __threadfence_block();
+}
+
+// The rest of the probe, in the wave's table in the workspace.
+__device__ __forceinline__ int visit_spill(int id, int* __restrict__ spill, uint32_t spill_mask, bool& spilled,
+                                           bool& overflow) {
   spilled = true;
   uint32_t g = (hash_id(id ^ 0x5bd1e995) >> 5) & spill_mask;
 #pragma unroll 1
@@ -605,6 +618,7 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
   int* spill = a.spill + (int64_t)wave_global * a.spill_slots;
   const uint32_t cap_mask = (uint32_t)a.vis_cap - 1u;
   const uint32_t spill_mask = (uint32_t)a.spill_slots - 1u;
+  bool spill_ready = false;  // this wave's workspace table has been emptied
   // screening lane roles: code lanes hold chunk ch of slot (p0 + l / cpr)
   constexpr int kChunk = chunk_elems<CODE>();
   const int cpr = a.cpr;
@@ -681,7 +695,8 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
 
     const int entry = a.entries ? a.entries[qi] : a.entry;
     if (l == 0) {
-      visit(entry, vis, cap_mask, a.vis_buckets, spill, spill_mask, spilled, overflow);
+      // (the table was just emptied: the entry lands in its first bucket)
+      visit_lds(entry, vis, cap_mask, a.vis_buckets);
       cid[0] = entry;
     }
     wave_lds_sync();
@@ -803,7 +818,17 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
       }
       // 3. visited test-and-set
       int isnew = 0;
-      if (nb >= 0) isnew = visit(nb, vis, cap_mask, a.vis_buckets, spill, spill_mask, spilled, overflow);
+      if (nb >= 0) isnew = visit_lds(nb, vis, cap_mask, a.vis_buckets);
+      if (ballot(isnew < 0) != 0ull) {
+        // the wave's workspace table holds whatever the caller's memory held
+        // until the wave first needs it; it is emptied then, and every query
+        // that used it empties it again at its end
+        if (!spill_ready) {
+          clear_spill(spill, a.spill_slots);
+          spill_ready = true;
+        }
+        if (isnew < 0) isnew = visit_spill(nb, spill, spill_mask, spilled, overflow);
+      }
       const uint64_t newm = ballot(isnew != 0);
       const int S = popc64(newm);
       n_vis += S;
@@ -1189,8 +1214,7 @@ __device__ __forceinline__ void search_body(const KArgs& a) {
     }
     if (any_spill) {
       // leave the spill table empty for the next query on this wave slot
-      for (int i = l; i < a.spill_slots; i += 64) spill[i] = -1;
-      __threadfence_block();
+      clear_spill(spill, a.spill_slots);
     }
     wave_lds_sync();
   }
