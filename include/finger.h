@@ -344,7 +344,8 @@ FINGER_API int finger_search(const finger_tables* t, const float* queries, int64
  * finger_search_noalloc_capacity() bytes (64 MiB) that the library holds on
  * each GPU it runs on until the process ends, instead of a caller workspace.
  * The call allocates nothing; the scratch parts that must start cleared are
- * cleared by fill kernels on `stream` at every call.  Every call on one GPU
+ * cleared at every call on `stream` (the queue counter by a fill kernel, each
+ * visited-set spill table by its search wave before first use).  Every call on one GPU
  * shares that GPU's array: calls that overlap on one GPU (other streams,
  * other threads) race and must be serialized by the caller.  Arguments,
  * results and errors as finger_search, plus EOVERFLOW when the search needs
