@@ -168,6 +168,33 @@ def test_results_independent_of_launch_geometry(api, mode):
             np.testing.assert_array_equal(x, y, err_msg=str(v))
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_spill_tables_start_from_any_workspace(api, mode):
+    """The visited-set spill tables live in the caller's workspace and are
+    not filled by the call: each search wave empties its own table the first
+    time it spills.  With spills forced by a tiny LDS table, a workspace full
+    of valid-looking node ids (the worst leftovers: a stale id would read as
+    visited) returns the same bits as a fresh one, on two calls in a row (the
+    second starts from the tables the first left behind)."""
+    import torch
+    _say(f"spill tables from a dirty workspace mode={mode}")
+    data, qs, G, _, piv = helpers.c2_small()
+    tab = api.finger_build_tables(_t(data), _t(G), rank=64 if mode else 0, pivots=piv)
+    base = dict(mode=mode, k=10, ef=96, entry=-1, visited_capacity=256, visited_probe=4, spill_capacity=4096)
+    ref = [x.cpu().numpy() for x in api.finger_search(tab, _t(qs), **base)]
+    assert (ref[2][:, 4] > 256).any(), "the case must spill"
+    p = api.search_params(**base)
+    need = api.finger_search_workspace_size(tab, qs.shape[0], p)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    ids = torch.randint(0, data.shape[0], ((need + 3) // 4,), dtype=torch.int32, device="cuda", generator=gen)
+    tab._ws = ids.view(torch.uint8)
+    for call in range(2):
+        got = [x.cpu().numpy() for x in api.finger_search(tab, _t(qs), p)]
+        for x, y in zip(ref, got):
+            np.testing.assert_array_equal(x, y, err_msg=f"call {call}")
+    tab.close()
+
+
 @pytest.mark.parametrize("code,rank", [(0, 32), (0, 64), (1, 32), (1, 64), (1, 128), (2, 32), (2, 64),
                                        (2, 128)])
 def test_screen_layouts_agree(api, code, rank):
